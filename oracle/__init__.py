@@ -1,0 +1,137 @@
+"""FP64 CPU oracle for NDGSBP decoding.
+
+TEST INFRASTRUCTURE ONLY: the tests, the package smoke check and the CPU
+baseline leg of the benchmark may call it; the decoder library never does.
+It shares no code with the HIP path. Pieces:
+
+* ``ndgsbp_ref.c`` (built to ``libndgsbp_ref.so``): Steps 2-4 of Sec. II-C
+  with eq. (1)-(3) in FP64, threaded over frames.
+* ``windows``: the contiguous CN windows with overlap (Python, below).
+* ``literal``: a pure-Python version of the same schedule over a pluggable
+  message algebra (real numbers or "which channel values reached here"
+  sets), used on tiny graphs to pin the schedule to the paper's Fig. 1
+  example.
+* ``bitmap``: brute-force bitwise MAP over all codewords (tiny codes).
+
+Parity status: every function here is pinned by tests under ``tests/``
+(see ``test_oracle_*``); the clamp constant (30) is a definition shared with
+the decoder, not something the paper fixes.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "ndgsbp_ref.c")
+_LIB = os.path.join(_HERE, "libndgsbp_ref.so")
+_lib = None
+
+XMAX = 30.0
+
+
+def build(force: bool = True) -> str:
+    """Compile the C oracle with gcc (-O2, IEEE semantics kept: no -ffast-math)."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-pthread",
+                               _SRC, "-o", tmp, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build(force=True)
+        lib = ctypes.CDLL(_LIB)
+        i32p = ctypes.POINTER(ctypes.c_int32)
+        lib.ref_decode.restype = ctypes.c_int
+        lib.ref_decode.argtypes = [ctypes.c_int, ctypes.c_int, i32p, i32p, ctypes.c_int, i32p, i32p,
+                                   ctypes.POINTER(ctypes.c_float), ctypes.c_int, ctypes.c_int,
+                                   ctypes.c_int, ctypes.POINTER(ctypes.c_double),
+                                   ctypes.POINTER(ctypes.c_uint8), i32p,
+                                   ctypes.POINTER(ctypes.c_uint8), ctypes.c_int]
+        lib.ref_phi_f64.restype = ctypes.c_double
+        lib.ref_phi_f64.argtypes = [ctypes.c_double]
+        lib.ref_boxplus.restype = ctypes.c_double
+        lib.ref_boxplus.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.c_int]
+        _lib = lib
+    return _lib
+
+
+def windows(M: int, G: int, overlap: int, wrap: bool = True):
+    """Contiguous CN windows (the grouping of Step 1 fixed to windows).
+
+    Window g starts at floor(g*M/G) and ends just before the next window's
+    start plus ``overlap`` CNs; with ``wrap`` the indices are taken mod M
+    (so the last window overlaps the first), without it the last window
+    stops at M."""
+    out = []
+    for g in range(G):
+        start = (g * M) // G
+        nxt = ((g + 1) * M) // G
+        if wrap or g < G - 1:
+            length = nxt - start + overlap
+        else:
+            length = M - start
+        if length > M:
+            raise ValueError("window longer than M")
+        idx = [(start + i) % M for i in range(length)] if wrap else \
+              [start + i for i in range(length) if start + i < M]
+        out.append(np.array(idx, dtype=np.int32))
+    return out
+
+
+def _groups_csr(groups):
+    gptr = np.zeros(len(groups) + 1, dtype=np.int32)
+    gptr[1:] = np.cumsum([len(g) for g in groups])
+    gcn = np.concatenate([np.asarray(g, dtype=np.int32) for g in groups]) if groups else \
+        np.zeros(0, np.int32)
+    return gptr, np.ascontiguousarray(gcn, dtype=np.int32)
+
+
+def _p(a, t):
+    return a.ctypes.data_as(ctypes.POINTER(t))
+
+
+def decode(code, groups, llr, max_iter: int, early_stop: bool, nthreads: int = 0):
+    """Run the FP64 oracle on float32 LLRs (F x n).
+
+    ``code`` has m, n, row_ptr, col_idx; ``groups`` is a list of CN-id arrays
+    processed in order. Returns dict(post=float64 (F,n), hard=uint8 (F,n),
+    iters=int32 (F,), syn_ok=uint8 (F,), threads=int)."""
+    lib = _load()
+    llr = np.ascontiguousarray(llr, dtype=np.float32)
+    if llr.ndim == 1:
+        llr = llr[None, :]
+    F, n = llr.shape
+    assert n == code.n
+    row_ptr = np.ascontiguousarray(code.row_ptr, dtype=np.int32)
+    col = np.ascontiguousarray(code.col_idx, dtype=np.int32)
+    gptr, gcn = _groups_csr(groups)
+    post = np.zeros((F, n), dtype=np.float64)
+    hard = np.zeros((F, n), dtype=np.uint8)
+    iters = np.zeros(F, dtype=np.int32)
+    syn = np.zeros(F, dtype=np.uint8)
+    i32 = ctypes.c_int32
+    rc = lib.ref_decode(code.m, n, _p(row_ptr, i32), _p(col, i32), len(groups), _p(gptr, i32),
+                        _p(gcn, i32), _p(llr, ctypes.c_float), F, int(max_iter), int(bool(early_stop)),
+                        _p(post, ctypes.c_double), _p(hard, ctypes.c_uint8), _p(iters, i32),
+                        _p(syn, ctypes.c_uint8), int(nthreads))
+    if rc < 0:
+        raise ValueError(f"ref_decode rejected its input ({rc})")
+    return dict(post=post, hard=hard, iters=iters, syn_ok=syn, threads=rc)
+
+
+def phi(x: float) -> float:
+    return _load().ref_phi_f64(float(x))
+
+
+def boxplus(xs) -> float:
+    a = np.ascontiguousarray(xs, dtype=np.float64)
+    return _load().ref_boxplus(_p(a, ctypes.c_double), len(a))

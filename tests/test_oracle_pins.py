@@ -1,0 +1,304 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix.
+
+Each check is independent of the oracle's own code: printed example sets
+(Sec. II-A, Fig. 1), exact MAP marginals on cycle-free graphs, textbook
+special cases (one group = flooding SPA, zero overlap = layered GSBP),
+closed forms of the CN update, and a high-SNR invariant.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import literal, bitmap
+from ldpcgen import Code, regular_code, make_frames
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _fig1():
+    with open(os.path.join(GOLD, "fig1_reach_sets.json")) as f:
+        return json.load(f)
+
+
+def _rows0(rows1):
+    return [[v - 1 for v in r] for r in rows1]
+
+
+# ---------------------------------------------------------------- Fig. 1 sets
+
+@pytest.mark.parametrize("sched", ["bp", "gsbp", "ndgsbp"])
+def test_fig1_reach_sets(sched):
+    g = _fig1()
+    rows = _rows0(g["graph_rows_1based"])
+    s = g["schedules"][sched]
+    groups = _rows0(s["groups_1based"])
+    trace = []
+    literal.run(rows, 8, groups, 1, literal.ReachAlgebra(), trace=trace)
+    for e in s["expect"]:
+        got = sorted(v + 1 for v in trace[e["after"] - 1][e["vn"] - 1])
+        assert got == e["set"], (sched, e, got)
+
+
+def _gauss_seidel_reach(rows, n, groups):
+    """Negative control: CNs of a group updated one after another, each
+    seeing its predecessors' VN updates (not the paper's schedule)."""
+    cols = [[] for _ in range(n)]
+    for m, r in enumerate(rows):
+        for v in r:
+            cols[v].append(m)
+    lcv = {(m, v): frozenset() for m, r in enumerate(rows) for v in r}
+    lvc = {(m, v): frozenset([v]) for m, r in enumerate(rows) for v in r}
+    trace = []
+    for grp in groups:
+        for m in grp:
+            for v in rows[m]:
+                lcv[(m, v)] = frozenset().union(*[lvc[(m, u)] for u in rows[m] if u != v])
+            for v in rows[m]:
+                for mm in cols[v]:
+                    lvc[(mm, v)] = frozenset([v]).union(*[lcv[(k, v)] for k in cols[v] if k != mm])
+        trace.append({v: frozenset().union(*[lcv[(m, v)] for m in cols[v]]) for v in range(n)})
+    return trace
+
+
+def test_fig1_sets_reject_sequential_within_group():
+    g = _fig1()
+    rows = _rows0(g["graph_rows_1based"])
+    s = g["schedules"]["ndgsbp"]
+    trace = _gauss_seidel_reach(rows, 8, _rows0(s["groups_1based"]))
+    mism = 0
+    for e in s["expect"]:
+        got = sorted(v + 1 for v in trace[e["after"] - 1][e["vn"] - 1])
+        mism += got != e["set"]
+    assert mism > 0
+
+
+def test_fig1_grouping_is_windows():
+    # (r, G, N_G) = (0.5, 3, 2) on M = 4: G*N_G - (G-1)*N_G*r = 6 - 2 = 4 = M,
+    # and the printed groups are contiguous windows without wraparound.
+    w = oracle.windows(4, 3, 1, wrap=False)
+    assert [list(x) for x in w] == [[0, 1], [1, 2], [2, 3]]
+    G, NG, r = 3, 2, 0.5
+    assert G * NG - (G - 1) * NG * r == 4
+
+
+# ------------------------------------------------------------- MAP on trees
+
+def _random_tree(rng, n_vn, max_dc=4):
+    """Random cycle-free Tanner graph: CNs attach one existing VN plus
+    fresh VNs until n_vn VNs exist."""
+    rows = []
+    nv = 1
+    while nv < n_vn:
+        k = int(rng.integers(1, min(max_dc, n_vn - nv + 1)))
+        old = int(rng.integers(0, nv))
+        rows.append([old] + list(range(nv, nv + k)))
+        nv += k
+    return rows
+
+
+def _code_from_rows(rows, n):
+    return Code.from_rows(rows, n)
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_c_oracle_equals_map_on_trees(seed):
+    rng = np.random.default_rng(100 + seed)
+    if seed == 0:
+        rows = _rows0(_fig1()["graph_rows_1based"])
+        n = 8
+    else:
+        n = int(rng.integers(8, 17))
+        rows = _random_tree(rng, n)
+    code = _code_from_rows(rows, n)
+    h = code.dense()
+    llr = rng.normal(1.0, 1.5, size=n).astype(np.float32)
+    want = bitmap.map_llr(h, llr.astype(np.float64))
+    m = code.m
+    schedules = {
+        "flooding": [np.arange(m)],
+        "gsbp": [np.arange(0, m // 2), np.arange(m // 2, m)] if m >= 2 else [np.arange(m)],
+        "ndgsbp": oracle.windows(m, max(1, min(3, m - 1)), 1, wrap=True) if m >= 3 else [np.arange(m)],
+    }
+    for name, groups in schedules.items():
+        out = oracle.decode(code, groups, llr[None], max_iter=2 * n, early_stop=False, nthreads=1)
+        np.testing.assert_allclose(out["post"][0], want, rtol=0, atol=1e-9, err_msg=name)
+
+
+def test_literal_equals_map_on_fig1():
+    rows = _rows0(_fig1()["graph_rows_1based"])
+    code = _code_from_rows(rows, 8)
+    rng = np.random.default_rng(7)
+    llr = rng.normal(0.8, 1.2, size=8)
+    want = bitmap.map_llr(code.dense(), llr)
+    for groups in ([[0, 1, 2, 3]], [[0, 1], [2, 3]], [[0, 1], [1, 2], [2, 3]]):
+        tot, _, _, _ = literal.run(rows, 8, groups, 6, literal.RealAlgebra(llr))
+        np.testing.assert_allclose(tot, want, atol=1e-10)
+
+
+# ------------------------------------------- C oracle vs literal (with cycles)
+
+def _random_code(rng, n, m, dc_lo=3, dc_hi=6):
+    rows = [sorted(rng.choice(n, size=int(rng.integers(dc_lo, dc_hi + 1)), replace=False))
+            for _ in range(m)]
+    return rows
+
+
+@pytest.mark.parametrize("seed", range(5))
+def test_c_oracle_matches_literal_schedule(seed):
+    rng = np.random.default_rng(200 + seed)
+    n = int(rng.integers(16, 30))
+    m = n // 2
+    rows = _random_code(rng, n, m)
+    code = _code_from_rows(rows, n)
+    G = int(rng.integers(2, 5))
+    o = int(rng.integers(1, 3))
+    groups = oracle.windows(m, G, o, wrap=True)
+    llr = rng.normal(0.6, 1.0, size=(3, n)).astype(np.float32)
+    iters = 4
+    out = oracle.decode(code, groups, llr, max_iter=iters, early_stop=False, nthreads=2)
+    for f in range(3):
+        tot, hard, _, ok = literal.run(rows, n, [list(g) for g in groups], iters,
+                                       literal.RealAlgebra(llr[f].astype(np.float64)))
+        np.testing.assert_allclose(out["post"][f], tot, rtol=1e-9, atol=1e-9)
+        assert list(out["hard"][f]) == hard
+        assert bool(out["syn_ok"][f]) == ok
+
+
+# ------------------------------------------------------ textbook special cases
+
+def _tanh_cn(x):
+    """Textbook CN rule on a vector: out_i = 2 atanh(prod_{j != i} tanh(x_j/2))."""
+    t = np.tanh(0.5 * np.asarray(x, dtype=np.float64))
+    out = np.empty(len(t))
+    for i in range(len(t)):
+        out[i] = 2.0 * np.arctanh(np.prod(np.delete(t, i)))
+    return out
+
+
+def _textbook_flooding(h, llr, iters):
+    """Two-phase flooding SPA on a dense H: all CNs, then all VNs."""
+    m, n = h.shape
+    mask = h.astype(bool)
+    q = np.where(mask, llr[None, :], 0.0)  # VN->CN
+    r = np.zeros((m, n))
+    for _ in range(iters):
+        for i in range(m):
+            idx = np.nonzero(mask[i])[0]
+            r[i, idx] = _tanh_cn(q[i, idx])
+        tot = llr + r.sum(axis=0)
+        q = np.where(mask, tot[None, :] - r, 0.0)
+    return llr + r.sum(axis=0)
+
+
+def _textbook_layered(h, llr, layers, iters):
+    """Posterior-form layered decoding: per layer, T = P - R on the layer's
+    edges, new R from T (all CNs of the layer at once), then P = L + sum R."""
+    m, n = h.shape
+    mask = h.astype(bool)
+    r = np.zeros((m, n))
+    p = llr.astype(np.float64).copy()
+    for _ in range(iters):
+        for layer in layers:
+            t = {i: p[np.nonzero(mask[i])[0]] - r[i, np.nonzero(mask[i])[0]] for i in layer}
+            for i in layer:
+                idx = np.nonzero(mask[i])[0]
+                r[i, idx] = _tanh_cn(t[i])
+            p = llr + r.sum(axis=0)
+    return p
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_one_group_is_flooding(seed):
+    code = regular_code(48, 3, 6, seed=300 + seed, girth6=False)
+    rng = np.random.default_rng(seed)
+    llr = rng.normal(0.7, 1.0, size=code.n).astype(np.float32)
+    out = oracle.decode(code, oracle.windows(code.m, 1, 0), llr[None], 5, False, 1)
+    want = _textbook_flooding(code.dense(), llr.astype(np.float64), 5)
+    np.testing.assert_allclose(out["post"][0], want, rtol=1e-9, atol=1e-9)
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_zero_overlap_is_layered_gsbp(seed):
+    code = regular_code(48, 3, 6, seed=310 + seed, girth6=False)
+    rng = np.random.default_rng(seed + 10)
+    llr = rng.normal(0.7, 1.0, size=code.n).astype(np.float32)
+    groups = oracle.windows(code.m, 4, 0)
+    out = oracle.decode(code, groups, llr[None], 4, False, 1)
+    want = _textbook_layered(code.dense(), llr.astype(np.float64), [list(g) for g in groups], 4)
+    np.testing.assert_allclose(out["post"][0], want, rtol=1e-9, atol=1e-9)
+
+
+def test_overlap_changes_the_result():
+    # the overlap schedule is not the disjoint one: same code, different output
+    code = regular_code(48, 3, 6, seed=320, girth6=False)
+    llr = np.random.default_rng(3).normal(0.5, 1.0, size=code.n).astype(np.float32)
+    a = oracle.decode(code, oracle.windows(code.m, 4, 0), llr[None], 1, False, 1)["post"]
+    b = oracle.decode(code, oracle.windows(code.m, 4, 3), llr[None], 1, False, 1)["post"]
+    assert np.max(np.abs(a - b)) > 1e-3
+
+
+# ------------------------------------------------------- CN update closed forms
+
+def test_phi_closed_forms():
+    # phi(x) = -ln tanh(x/2): phi(ln 3) = ln 2, and phi is an involution
+    assert abs(oracle.phi(math.log(3.0)) - math.log(2.0)) < 1e-15
+    for x in [1e-6, 1e-3, 0.1, 0.8813735870195430, 1.0, 5.0, 20.0, 29.9]:
+        assert abs(oracle.phi(oracle.phi(x)) - x) <= 1e-12 * max(1.0, x)
+        # phi(x) = -ln tanh(x/2) = 2 atanh(exp(-x)); each form where FP64 holds it well
+        ref = -math.log(math.tanh(x / 2)) if x < 1.0 else 2 * math.atanh(math.exp(-x))
+        assert abs(oracle.phi(x) - ref) <= 1e-13 * ref
+
+
+def test_boxplus_closed_forms():
+    rng = np.random.default_rng(11)
+    # one input (a degree-2 check): the message is the other input
+    for x in rng.normal(0, 5, size=20):
+        assert abs(oracle.boxplus([x]) - x) <= 1e-12 * max(1.0, abs(x))
+    # two inputs (degree 3): 2 atanh(tanh(a/2) tanh(b/2))
+    for a, b in rng.normal(0, 3, size=(20, 2)):
+        want = 2 * math.atanh(math.tanh(a / 2) * math.tanh(b / 2))
+        assert abs(oracle.boxplus([a, b]) - want) <= 1e-10 * max(1.0, abs(want))
+    # sign rule: product of signs, -0.0 counts as positive
+    assert oracle.boxplus([-1.0, 2.0]) < 0
+    assert oracle.boxplus([-1.0, -2.0]) > 0
+    assert oracle.boxplus([-0.0, 2.0]) > 0
+    # clamp: magnitudes stay in [phi(30), 30]
+    # both inputs clamp to 30: phi(2 phi(30)) = 30 - ln 2 to first order in e^-30
+    assert abs(oracle.boxplus([50.0, 60.0]) - (30.0 - math.log(2.0))) < 1e-9
+    assert abs(oracle.boxplus([]) - 30.0) < 1e-9  # a degree-1 check forces its bit
+    assert abs(oracle.boxplus([0.0, 3.0])) <= oracle.phi(30.0) * 1.0001
+
+
+# ------------------------------------------------------------ invariants
+
+def test_high_snr_all_zero_decodes_in_one_iteration():
+    code = regular_code(2304, 3, 6, seed=1001)
+    for ebn0, it_max in ((6.0, 3), (10.0, 1)):
+        llr, cw = make_frames(code.n, 8, ebn0, 0.5, seed=77)
+        out = oracle.decode(code, oracle.windows(code.m, 8, 16), llr, 20, True, 4)
+        assert np.all(out["syn_ok"] == 1)
+        assert np.all(out["iters"] <= it_max)
+        assert np.all(out["hard"] == 0)
+
+
+def test_early_stop_iteration_count_is_first_zero_syndrome():
+    code = regular_code(96, 3, 6, seed=1000)
+    llr, _ = make_frames(code.n, 40, 2.0, 0.5, seed=5)
+    groups = oracle.windows(code.m, 4, 2)
+    es = oracle.decode(code, groups, llr, 10, True, 2)
+    for f in range(40):
+        it = int(es["iters"][f])
+        assert 1 <= it <= 10
+        if es["syn_ok"][f]:
+            # the same frame run for exactly `it` iterations without early stop
+            # ends with the same decision, and one iteration fewer had not converged
+            fx = oracle.decode(code, groups, llr[f:f + 1], it, False, 1)
+            assert fx["syn_ok"][0] == 1
+            assert np.array_equal(fx["hard"][0], es["hard"][f])
+            if it > 1:
+                fp = oracle.decode(code, groups, llr[f:f + 1], it - 1, False, 1)
+                assert fp["syn_ok"][0] == 0
