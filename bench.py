@@ -1,0 +1,179 @@
+"""Throughput of NDGSBP decoding on one MI355X.
+
+Workload (one step): the (3,6)-regular n=2304 code (m=1152, 4-cycle-free,
+seeded), 8 CN windows of 160 CNs with a 16-CN overlap (wraparound), 16384
+frames of random information bits at each Eb/N0 in 1.0, 1.25, ..., 2.5 dB
+(114688 frames), BPSK/AWGN, at most 20 iterations with the syndrome stop of
+Step 4. All LLRs are resident in HBM before timing starts; one step is one
+decode call over all frames (hard decisions, posteriors, iteration counts
+and syndrome flags written back to HBM).
+
+Prints one JSON line. The decoded info rate counts K = 1152 information bits
+per frame. The roofline object is for the decode kernel, bound by VALU issue
+(see the derivation of the per-edge-update slot count in the design doc).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "decoded info Gbit/s at matched FER (served/batched vs plain); p50/p99 latency"
+
+# VALU issue slots per edge update that the method itself needs: two phi
+# evaluations of 1 exp + 1 log + 1 reciprocal (transcendentals issue at half
+# the full FP32 rate on gfx950, 2 slots each) plus three full-rate ops each,
+# and eight full-rate ops for the extrinsic, clamps, exclusive sum, signs and
+# add-back: 2 * (6 + 3) + 8 = 26; see the design doc.
+SLOTS_PER_EDGE_UPDATE = 26
+# 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz, one non-packed VALU op per lane-cycle
+PEAK_SLOTS_PER_S = 256 * 4 * 16 * 2.4e9
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def make_inputs(rec, frames_per_snr):
+    from ldpcgen import workloads as W
+    llrs, cws = [], []
+    for i in range(len(rec["ebn0"])):
+        llr, cw = W.frames(rec, i, num_frames=frames_per_snr)
+        llrs.append(llr)
+        cws.append(cw)
+    return np.concatenate(llrs), np.concatenate(cws)
+
+
+def cpu_baseline(code, groups, llr, rec, frames_per_snr, sample_per_snr, k_info):
+    import oracle
+    idx = np.concatenate([np.arange(sample_per_snr) + i * frames_per_snr
+                          for i in range(len(rec["ebn0"]))])
+    t0 = time.perf_counter()
+    out = oracle.decode(code, groups, llr[idx], rec["max_iter"], rec["early_stop"], nthreads=0)
+    dt = time.perf_counter() - t0
+    return dict(value=len(idx) * k_info / dt / 1e9, unit="Gbit/s", cores=int(out["threads"]),
+                kind="oracle",
+                sample=f"first {sample_per_snr} frames of each of the {len(rec['ebn0'])} Eb/N0 "
+                       f"points ({len(idx)} frames), FP64, {dt:.1f} s",
+                seconds=dt)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--msg", default="fp32", choices=["fp32", "fp16", "bf16"])
+    ap.add_argument("--frames-per-snr", type=int, default=16384)
+    ap.add_argument("--cpu-sample-per-snr", type=int, default=160)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fixed", action="store_true", help="skip the fixed-iteration pass")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
+              "(the decoder has no multi-GPU path in this build)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_1202_1060_amd as nd
+    from ldpcgen import workloads as W
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    rec = W.SWEEP
+    code = W.CODES[rec["code"]]()
+    enc = W.encoder_for(rec["code"])
+    t0 = time.perf_counter()
+    llr_np, cw_np = make_inputs(rec, args.frames_per_snr)
+    log(f"inputs: {llr_np.shape} in {time.perf_counter() - t0:.1f} s")
+    F = llr_np.shape[0]
+    dcode = nd.Code(code, windows=rec["windows"])
+    e_iter = dcode.info["edge_updates"]
+    llr = torch.from_numpy(llr_np).to(dev)
+    out = dict(hard=torch.empty((F, code.n), dtype=torch.uint8, device=dev),
+               post=torch.empty((F, code.n), dtype=torch.float32, device=dev),
+               iters=torch.empty((F,), dtype=torch.int32, device=dev),
+               syn_ok=torch.empty((F,), dtype=torch.uint8, device=dev))
+    stream = torch.cuda.current_stream(dev)
+
+    def run(steps, early_stop):
+        evs = []
+        for _ in range(steps):
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            nd.decode(dcode, llr, rec["max_iter"], early_stop=early_stop, msg=args.msg, out=out,
+                      stream=stream)
+            b.record(stream)
+            evs.append((a, b))
+        return evs
+
+    run(args.warmup, True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    evs = run(args.steps, True)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kern_ms = float(np.mean([a.elapsed_time(b) for a, b in evs]))
+    iters = out["iters"].cpu().numpy()
+    hard = out["hard"].cpu().numpy()
+    ms_per_step = wall * 1e3 / args.steps
+    bits = F * enc.k
+    value = bits / (wall / args.steps) / 1e9
+    edge_updates = float(iters.astype(np.int64).sum()) * e_iter
+    achieved = edge_updates * SLOTS_PER_EDGE_UPDATE / (kern_ms * 1e-3)
+    # FER per Eb/N0 point against the transmitted codewords
+    fer = []
+    for i, eb in enumerate(rec["ebn0"]):
+        sl = slice(i * args.frames_per_snr, (i + 1) * args.frames_per_snr)
+        errs = np.any(hard[sl] != cw_np[sl], axis=1)
+        fer.append(dict(ebn0=eb, fer=float(errs.mean()), mean_iters=float(iters[sl].mean())))
+    result = {
+        "metric": METRIC, "value": round(value, 4), "unit": "Gbit/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32" if args.msg == "fp32" else f"f32 compute, {args.msg} messages",
+        "data": "synthetic",
+        "config": {"workload": "NDGSBP, (3,6)-regular n=2304 code, 8 CN windows of 160 with 16 overlap "
+                               "(wrap), Eb/N0 1.0-2.5 dB step 0.25 x 16384 frames, I_max 20, "
+                               "syndrome stop",
+                   "frames_per_step": F, "k_info": enc.k, "n": code.n, "max_iter": rec["max_iter"],
+                   "early_stop": True, "msg": args.msg},
+        "edge_updates_per_s": edge_updates / (kern_ms * 1e-3),
+        "mean_iters": float(iters.mean()),
+        "kernel_ms": kern_ms,
+        "fer": fer,
+        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_SLOTS_PER_S / 1e12,
+                     "unit": "T VALU-slots/s", "frac": achieved / PEAK_SLOTS_PER_S, "traffic": None},
+    }
+    if not args.no_fixed:
+        run(1, False)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        fevs = run(max(1, args.steps // 2), False)
+        torch.cuda.synchronize()
+        fwall = (time.perf_counter() - t1) / len(fevs)
+        fk = float(np.mean([a.elapsed_time(b) for a, b in fevs]))
+        fe = F * rec["max_iter"] * e_iter
+        result["fixed_iterations"] = {
+            "gbit_s": bits / fwall / 1e9, "kernel_ms": fk,
+            "edge_updates_per_s": fe / (fk * 1e-3),
+            "roofline_frac": fe * SLOTS_PER_EDGE_UPDATE / (fk * 1e-3) / PEAK_SLOTS_PER_S}
+    if not args.no_cpu_baseline:
+        import oracle
+        groups = oracle.windows(code.m, *rec["windows"][:2], bool(rec["windows"][2]))
+        result["cpu_baseline"] = cpu_baseline(code, groups, llr_np, rec, args.frames_per_snr,
+                                              args.cpu_sample_per_snr, enc.k)
+    dcode.close()
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -128,6 +128,27 @@ def decode(code, groups, llr, max_iter: int, early_stop: bool, nthreads: int = 0
     return dict(post=post, hard=hard, iters=iters, syn_ok=syn, threads=rc)
 
 
+def perturb_one_ulp(llr, seed: int = 12345):
+    """The same float32 LLRs, each moved by one ulp up or down (seeded)."""
+    llr = np.ascontiguousarray(llr, dtype=np.float32)
+    d = np.random.default_rng(seed).choice(np.array([-np.inf, np.inf], np.float32), size=llr.shape)
+    return np.nextafter(llr, d).astype(np.float32)
+
+
+def decode_with_sensitivity(code, groups, llr, max_iter: int, early_stop: bool, nthreads: int = 0):
+    """Oracle result plus each frame's conditioning: ``sens[f]`` is the largest
+    posterior change when every input LLR moves by one float32 ulp (inf when
+    that already changes a hard decision). It measures how strongly the FP64
+    decode amplifies rounding-sized input changes on that frame."""
+    ref = decode(code, groups, llr, max_iter, early_stop, nthreads)
+    ctl = decode(code, groups, perturb_one_ulp(llr), max_iter, early_stop, nthreads)
+    sens = np.abs(ctl["post"] - ref["post"]).max(axis=1)
+    flip = np.any(ctl["hard"] != ref["hard"], axis=1) | (ctl["iters"] != ref["iters"])
+    sens[flip] = np.inf
+    ref["sens"] = sens
+    return ref
+
+
 def phi(x: float) -> float:
     return _load().ref_phi_f64(float(x))
 

@@ -1,0 +1,134 @@
+"""MI355X (gfx950) NDGSBP LDPC decoder: thin Python binding of libndgsbp.so.
+
+The functions keep the C names (``ldpc_code_create``, ``ldpc_decode`` ...)
+and only marshal arguments; every step of the decode runs in the HIP
+kernels. PyTorch supplies device memory and streams. Importing this package
+imports torch first so that the library binds to the HIP runtime torch has
+loaded.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+import torch  # noqa: F401  (must precede loading the library)
+
+from . import _native
+from ._native import (LdpcError, LDPC_OK, LDPC_EINVAL, LDPC_ENOMEM, LDPC_EHIP,
+                      LDPC_EUNSUPPORTED, LDPC_GROUPS_WINDOWS, LDPC_GROUPS_EXPLICIT,
+                      LDPC_FLAG_EARLY_STOP, LDPC_FLAG_MSG_FP16, LDPC_FLAG_MSG_BF16)
+
+__all__ = [
+    "Code", "ldpc_code_create", "ldpc_code_destroy", "ldpc_code_query", "ldpc_decode",
+    "ldpc_last_error", "decode", "LdpcError", "msg_flag",
+    "LDPC_FLAG_EARLY_STOP", "LDPC_FLAG_MSG_FP16", "LDPC_FLAG_MSG_BF16",
+]
+
+
+
+def _i32(a):
+    return np.ascontiguousarray(a, dtype=np.int32)
+
+
+def _ptr(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+
+
+def ldpc_last_error() -> str:
+    return _native.load().ldpc_last_error().decode(errors="replace")
+
+
+def ldpc_code_create(m, n, row_ptr, col_idx, *, windows=None, groups=None, device=0):
+    """Create a device code handle (see include/ndgsbp.h).
+
+    ``windows=(G, overlap, wrap)`` or ``groups=[CN-id arrays]`` (in order).
+    Returns the opaque handle (int)."""
+    rp, ci = _i32(row_ptr), _i32(col_idx)
+    h = _native.ldpc_h_csr(int(m), int(n), int(len(ci)), _ptr(rp), _ptr(ci))
+    if (windows is None) == (groups is None):
+        raise ValueError("give exactly one of windows= or groups=")
+    keep = []
+    if windows is not None:
+        G, o, wrap = windows
+        g = _native.ldpc_grouping(LDPC_GROUPS_WINDOWS, int(G), int(o), int(bool(wrap)), None, None)
+    else:
+        gptr = _i32(np.concatenate([[0], np.cumsum([len(x) for x in groups])]))
+        gcn = _i32(np.concatenate([np.asarray(x) for x in groups]) if len(groups) else [])
+        keep += [gptr, gcn]
+        g = _native.ldpc_grouping(LDPC_GROUPS_EXPLICIT, len(groups), 0, 0, _ptr(gptr), _ptr(gcn))
+    out = ctypes.c_void_p()
+    _native.check(_native.load().ldpc_code_create(ctypes.byref(h), ctypes.byref(g), int(device), ctypes.byref(out)))
+    return out.value
+
+
+def ldpc_code_destroy(handle) -> None:
+    _native.check(_native.load().ldpc_code_destroy(ctypes.c_void_p(handle)))
+
+
+def ldpc_code_query(handle) -> dict:
+    info = _native.ldpc_code_info()
+    _native.check(_native.load().ldpc_code_query(ctypes.c_void_p(handle), ctypes.byref(info)))
+    return {k: getattr(info, k) for k, _ in info._fields_}
+
+
+def ldpc_decode(handle, llr_ptr, num_frames, max_iter, flags, hard_ptr, post_ptr, iters_ptr,
+                syn_ok_ptr, stream) -> None:
+    """Raw entry point: device pointers as ints (0 for NULL), stream handle as int."""
+    _native.check(_native.load().ldpc_decode(ctypes.c_void_p(handle), ctypes.c_void_p(llr_ptr),
+                                   int(num_frames), int(max_iter), int(flags),
+                                   ctypes.c_void_p(hard_ptr), ctypes.c_void_p(post_ptr or None),
+                                   ctypes.c_void_p(iters_ptr), ctypes.c_void_p(syn_ok_ptr or None),
+                                   ctypes.c_void_p(stream or None)))
+
+
+def msg_flag(msg: str) -> int:
+    return {"fp32": 0, "fp16": LDPC_FLAG_MSG_FP16, "bf16": LDPC_FLAG_MSG_BF16}[msg]
+
+
+class Code:
+    """Owns a device code handle. ``code`` is any object with m, n, row_ptr,
+    col_idx (e.g. ldpcgen.Code)."""
+
+    def __init__(self, code, *, windows=None, groups=None, device=0):
+        self.m, self.n = int(code.m), int(code.n)
+        self.handle = ldpc_code_create(code.m, code.n, code.row_ptr, code.col_idx,
+                                       windows=windows, groups=groups, device=device)
+        self.info = ldpc_code_query(self.handle)
+        self.device = device
+
+    def close(self):
+        if getattr(self, "handle", None):
+            ldpc_code_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def decode(code: Code, llr: torch.Tensor, max_iter: int, *, early_stop: bool = True,
+           msg: str = "fp32", want_post: bool = True, want_syn: bool = True, out=None,
+           stream=None):
+    """Decode a (F, n) float32 device tensor; returns dict of device tensors
+    hard (uint8), post (float32, optional), iters (int32), syn_ok (uint8)."""
+    if llr.dtype != torch.float32 or llr.dim() != 2 or llr.shape[1] != code.n:
+        raise ValueError("llr must be a (F, n) float32 tensor")
+    if not llr.is_cuda or not llr.is_contiguous():
+        raise ValueError("llr must be a contiguous device tensor")
+    F = llr.shape[0]
+    dev = llr.device
+    if out is None:
+        out = dict(hard=torch.empty((F, code.n), dtype=torch.uint8, device=dev),
+                   post=torch.empty((F, code.n), dtype=torch.float32, device=dev) if want_post else None,
+                   iters=torch.empty((F,), dtype=torch.int32, device=dev),
+                   syn_ok=torch.empty((F,), dtype=torch.uint8, device=dev) if want_syn else None)
+    flags = msg_flag(msg) | (LDPC_FLAG_EARLY_STOP if early_stop else 0)
+    s = stream if stream is not None else torch.cuda.current_stream(dev)
+    ldpc_decode(code.handle, llr.data_ptr(), F, max_iter, flags, out["hard"].data_ptr(),
+                out["post"].data_ptr() if out.get("post") is not None else 0,
+                out["iters"].data_ptr(),
+                out["syn_ok"].data_ptr() if out.get("syn_ok") is not None else 0,
+                s.cuda_stream)
+    return out

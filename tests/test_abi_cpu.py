@@ -1,0 +1,106 @@
+"""C ABI checks that need no GPU: the library loads, exports every symbol
+the header declares, and rejects malformed input before touching a device."""
+import ctypes
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "ndgsbp.h")
+
+
+def _declared():
+    src = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:int|const char\*|void)\s+(ldpc_\w+)\s*\(", src, re.M)))
+
+
+def test_header_declares_the_abi():
+    assert _declared() == sorted(["ldpc_code_create", "ldpc_code_destroy", "ldpc_code_query",
+                                  "ldpc_decode", "ldpc_last_error"])
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_1202_1060_amd import _native
+    assert os.path.exists(_native.LIB_PATH), "build the library first"
+    out = subprocess.run(["nm", "-D", "--defined-only", _native.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    exported = set(re.findall(r" T (ldpc_\w+)", out))
+    for sym in _declared():
+        assert sym in exported, sym
+    assert set(_native.EXPORTS) == set(_declared())
+
+
+def test_header_compiles_as_c():
+    src = '#include "ndgsbp.h"\nint main(void){ldpc_code_t c = 0; (void)c; return LDPC_OK;}\n'
+    res = subprocess.run(["gcc", "-std=c99", "-Wall", "-Werror", "-I", os.path.join(ROOT, "include"),
+                          "-x", "c", "-", "-o", "/dev/null"], input=src, text=True, capture_output=True)
+    assert res.returncode == 0, res.stderr
+
+
+@pytest.fixture(scope="module")
+def nd():
+    import paper_1202_1060_amd as mod
+    return mod
+
+
+def _create(nd, m, n, row_ptr, col, windows=(1, 0, 0), groups=None):
+    if groups is not None:
+        return nd.ldpc_code_create(m, n, row_ptr, col, groups=groups)
+    return nd.ldpc_code_create(m, n, row_ptr, col, windows=windows)
+
+
+@pytest.mark.parametrize("case", [
+    "bad_row_ptr", "col_out_of_range", "dup_in_row", "overlap_too_big", "cn_uncovered",
+    "cn_twice_in_group", "group_cn_range", "negative_overlap", "too_many_windows",
+])
+def test_create_rejects_malformed_input(nd, case):
+    rp = [0, 2, 4, 6]
+    col = [0, 1, 1, 2, 2, 3]
+    m, n = 3, 4
+    kw = {}
+    if case == "bad_row_ptr":
+        rp = [0, 3, 2, 6]
+    elif case == "col_out_of_range":
+        col = [0, 1, 1, 2, 2, 4]
+    elif case == "dup_in_row":
+        col = [0, 0, 1, 2, 2, 3]
+    elif case == "overlap_too_big":
+        kw = dict(windows=(1, 1, 1))
+    elif case == "cn_uncovered":
+        kw = dict(groups=[[0, 1]])
+    elif case == "cn_twice_in_group":
+        kw = dict(groups=[[0, 1, 1, 2]])
+    elif case == "group_cn_range":
+        kw = dict(groups=[[0, 1, 2, 3]])
+    elif case == "negative_overlap":
+        kw = dict(windows=(2, -1, 1))
+    elif case == "too_many_windows":
+        kw = dict(windows=(4, 0, 1))
+    with pytest.raises(nd.LdpcError) as ei:
+        _create(nd, m, n, rp, col, **kw)
+    assert ei.value.code == nd.LDPC_EINVAL
+    assert nd.ldpc_last_error()
+
+
+def test_unsupported_sizes(nd):
+    # n above 16-bit VN ids, and a CN of degree 33
+    with pytest.raises(nd.LdpcError) as ei:
+        _create(nd, 1, 70000, [0, 2], [0, 69999])
+    assert ei.value.code == nd.LDPC_EUNSUPPORTED
+    with pytest.raises(nd.LdpcError) as ei:
+        _create(nd, 1, 40, [0, 33], list(range(33)))
+    assert ei.value.code == nd.LDPC_EUNSUPPORTED
+
+
+def test_decode_rejects_null_code(nd):
+    with pytest.raises(nd.LdpcError) as ei:
+        nd.ldpc_decode(0, 0, 1, 10, 0, 0, 0, 0, 0, 0)
+    assert ei.value.code == nd.LDPC_EINVAL
+
+
+def test_destroy_null_is_ok(nd):
+    from paper_1202_1060_amd import _native
+    assert _native.load().ldpc_code_destroy(None) == 0

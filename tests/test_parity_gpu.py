@@ -1,0 +1,188 @@
+"""Parity of the HIP decoder (through the C ABI) with the FP64 oracle."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover - GPU machine only
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+import oracle  # noqa: E402
+import paper_1202_1060_amd as nd  # noqa: E402
+from ldpcgen import Code, regular_code, make_frames  # noqa: E402
+from ldpcgen import workloads as W  # noqa: E402
+
+from parity import gpu_decode, compare  # noqa: E402
+
+
+def _groups(code, windows):
+    G, o, wrap = windows
+    return oracle.windows(code.m, G, o, bool(wrap))
+
+
+def _run_both(code, windows, llr, max_iter, early_stop, msg="fp32", nthreads=0):
+    dcode = nd.Code(code, windows=windows)
+    try:
+        g = gpu_decode(dcode, llr, max_iter, early_stop, msg)
+    finally:
+        dcode.close()
+    r = oracle.decode_with_sensitivity(code, _groups(code, windows), llr, max_iter, early_stop, nthreads)
+    return g, r
+
+
+def test_small_workload():
+    rec = W.SMALL
+    code = W.CODES[rec["code"]]()
+    llr, _ = W.frames(rec, 0)
+    g, r = _run_both(code, rec["windows"], llr, rec["max_iter"], rec["early_stop"])
+    st = compare(g, r)
+    print("small", st)
+    assert np.all(g["iters"] == rec["max_iter"])
+
+
+@pytest.mark.parametrize("snr", range(7))
+def test_sweep_early_stop(snr):
+    rec = W.SWEEP
+    code = W.CODES[rec["code"]]()
+    llr, _ = W.frames(rec, snr, num_frames=160)
+    g, r = _run_both(code, rec["windows"], llr, rec["max_iter"], True)
+    print("sweep", rec["ebn0"][snr], compare(g, r))
+
+
+@pytest.mark.parametrize("snr", [0, 3])
+def test_sweep_fixed_iterations(snr):
+    rec = W.SWEEP
+    code = W.CODES[rec["code"]]()
+    llr, _ = W.frames(rec, snr, num_frames=96, first_frame=1000)
+    g, r = _run_both(code, rec["windows"], llr, rec["max_iter"], False)
+    print("fixed", rec["ebn0"][snr], compare(g, r))
+    assert np.all(g["iters"] == rec["max_iter"])
+
+
+@pytest.mark.parametrize("recipe", ["flooding", "gsbp"])
+def test_baseline_schedules(recipe):
+    rec = W.SWEEP_FLOODING if recipe == "flooding" else W.SWEEP_GSBP
+    code = W.CODES[rec["code"]]()
+    llr, _ = W.frames(rec, 2, num_frames=128)
+    g, r = _run_both(code, rec["windows"], llr, rec["max_iter"], True)
+    print(recipe, compare(g, r))
+
+
+def test_full_batch_sampled_frames():
+    """All 16384 frames of one Eb/N0 point in one launch; the oracle checks
+    a random sample of them."""
+    rec = W.SWEEP
+    code = W.CODES[rec["code"]]()
+    llr, _ = W.frames(rec, 2)
+    dcode = nd.Code(code, windows=rec["windows"])
+    g = gpu_decode(dcode, llr, rec["max_iter"], True)
+    dcode.close()
+    idx = np.sort(np.random.default_rng(1).choice(llr.shape[0], size=48, replace=False))
+    r = oracle.decode_with_sensitivity(code, _groups(code, rec["windows"]), llr[idx], rec["max_iter"], True)
+    print("sampled", compare({k: v[idx] for k, v in g.items()}, r))
+    assert g["iters"].min() >= 1 and g["iters"].max() <= rec["max_iter"]
+
+
+def test_qc_code_fp32():
+    rec = W.PRECISION
+    code = W.CODES[rec["code"]]()
+    llr, _ = W.frames(rec, 0, num_frames=128)
+    g, r = _run_both(code, rec["windows"], llr, rec["max_iter"], True)
+    print("qc", compare(g, r))
+
+
+def test_deterministic_bitwise():
+    rec = W.SWEEP
+    code = W.CODES[rec["code"]]()
+    llr, _ = W.frames(rec, 1, num_frames=256)
+    dcode = nd.Code(code, windows=rec["windows"])
+    a = gpu_decode(dcode, llr, rec["max_iter"], True)
+    b = gpu_decode(dcode, llr, rec["max_iter"], True)
+    dcode.close()
+    for k in a:
+        assert np.array_equal(a[k], b[k]), k
+
+
+def test_explicit_groups_equal_windows():
+    rec = W.SWEEP
+    code = W.CODES[rec["code"]]()
+    llr, _ = W.frames(rec, 1, num_frames=64)
+    a_code = nd.Code(code, windows=rec["windows"])
+    b_code = nd.Code(code, groups=_groups(code, rec["windows"]))
+    a = gpu_decode(a_code, llr, rec["max_iter"], True)
+    b = gpu_decode(b_code, llr, rec["max_iter"], True)
+    a_code.close()
+    b_code.close()
+    for k in a:
+        assert np.array_equal(a[k], b[k]), k
+
+
+@pytest.mark.parametrize("windows", [(5, 3, 1), (5, 3, 0), (7, 0, 1), (1, 0, 0), (48, 1, 1)])
+def test_ragged_and_degenerate_windows(windows):
+    """M=48 split unevenly, no wraparound, single-CN windows, one window."""
+    code = W.code_n96()
+    llr, _ = make_frames(code.n, 64, 1.5, 0.5, seed=31)
+    g, r = _run_both(code, windows, llr, 8, True)
+    print(windows, compare(g, r))
+
+
+def test_low_and_high_degree_checks():
+    """Degree-1 and degree-2 checks and a degree-20 check in one code."""
+    rng = np.random.default_rng(4)
+    n = 60
+    rows = [[0], [1, 2], [3, 4]] + [sorted(rng.choice(n, size=int(rng.integers(3, 8)), replace=False))
+                                     for _ in range(24)]
+    rows.append(sorted(rng.choice(n, size=20, replace=False)))
+    code = Code.from_rows(rows, n)
+    llr, _ = make_frames(n, 64, 2.0, 0.5, seed=32)
+    g, r = _run_both(code, (4, 2, 1), llr, 10, False)
+    print("degrees", compare(g, r))
+
+
+def test_tree_code_reaches_map():
+    from oracle import bitmap
+    rows = [[0, 1, 2], [1, 3, 4], [3, 5, 6], [6, 7]]
+    code = Code.from_rows(rows, 8)
+    rng = np.random.default_rng(9)
+    llr = rng.normal(1.0, 1.5, size=(32, 8)).astype(np.float32)
+    dcode = nd.Code(code, groups=[[0, 1], [1, 2], [2, 3]])
+    g = gpu_decode(dcode, llr, 8, False)
+    dcode.close()
+    for f in range(32):
+        want = bitmap.map_llr(code.dense(), llr[f].astype(np.float64))
+        np.testing.assert_allclose(g["post"][f], want, rtol=1e-4, atol=1e-4)
+
+
+def test_zero_and_one_frame():
+    code = W.code_n96()
+    dcode = nd.Code(code, windows=(4, 2, 1))
+    empty = torch.empty((0, code.n), dtype=torch.float32, device="cuda:0")
+    out = nd.decode(dcode, empty, 10)
+    torch.cuda.synchronize()
+    assert out["hard"].shape == (0, code.n)
+    llr, _ = make_frames(code.n, 1, 2.0, 0.5, seed=3)
+    g = gpu_decode(dcode, llr, 10, False)
+    dcode.close()
+    r = oracle.decode_with_sensitivity(code, _groups(code, (4, 2, 1)), llr, 10, False)
+    compare(g, r)
+
+
+def test_largest_code_that_fits_and_one_that_does_not():
+    # n = 8064 QC rate-1/2 code (z = 336) fits one frame in LDS with FP16 messages
+    code = W.code_qc(8064, "1/2", 1100)
+    dcode = nd.Code(code, windows=(12, 84, 1))
+    info = dcode.info
+    llr, _ = make_frames(code.n, 16, 2.0, 0.5, seed=33)
+    g = gpu_decode(dcode, llr, 10, True, msg="fp16")
+    assert g["iters"].min() >= 1
+    dcode.close()
+    # n = 60000: the posteriors alone exceed the LDS of one workgroup
+    big = regular_code(60000, 3, 6, seed=7, girth6=False)
+    bcode = nd.Code(big, windows=(8, 0, 1))
+    x = torch.zeros((1, big.n), dtype=torch.float32, device="cuda:0")
+    with pytest.raises(nd.LdpcError) as ei:
+        nd.decode(bcode, x, 5)
+    assert ei.value.code == nd.LDPC_EUNSUPPORTED
+    bcode.close()
+    print("lds per frame (fp32, 16-bit):", info["lds_bytes_fp32"], info["lds_bytes_16"])
