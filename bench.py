@@ -75,6 +75,8 @@ def main():
     ap.add_argument("--cpu-sample-per-snr", type=int, default=160)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fixed", action="store_true", help="skip the fixed-iteration pass")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a plain 1 GiB device copy (for scaling HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
@@ -87,6 +89,16 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
+    if args.calibrate_copy:
+        # one device-to-device copy of 1 GiB: the counters of this dispatch read
+        # 1 GiB fetched and 1 GiB written
+        x = torch.ones(1 << 28, dtype=torch.float32, device=dev)
+        y = torch.empty_like(x)
+        torch.cuda.synchronize()
+        y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibrate_copy_bytes": x.numel() * 4}), flush=True)
+        return
     rec = W.SWEEP
     code = W.CODES[rec["code"]]()
     enc = W.encoder_for(rec["code"])

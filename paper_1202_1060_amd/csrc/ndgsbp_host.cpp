@@ -4,6 +4,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
@@ -60,6 +61,7 @@ void free_tables(DeviceTables& t) {
     (void)hipFree(t.fix);
     (void)hipFree(t.fix_ptr);
     (void)hipFree(t.syn_col);
+    (void)hipFree(t.work);
     t = DeviceTables{};
 }
 
@@ -120,20 +122,62 @@ int expand_groups(const ldpc_grouping* g, int m, std::vector<std::vector<int32_t
     return LDPC_OK;
 }
 
-// LDS of one frame: posteriors (n + 2 floats, two flags), delta slots,
-// messages (m * D).
-size_t p_bytes(const ldpc_code* c) { return align16((size_t)(c->n + 4) * 4); }
-size_t ds_bytes(const ldpc_code* c) { return align16((size_t)c->max_slots * 4); }
-size_t lds_bytes(const ldpc_code* c, MsgKind kind) {
-    const size_t msg = kind == kMsgF32 ? 4 : 2;
-    return p_bytes(c) + ds_bytes(c) + align16((size_t)c->m * c->D * msg);
+// LDS of a workgroup with S frame slots (layout in ndgsbp_internal.h).
+size_t float_bytes(const ldpc_code* c, int S) { return align16((size_t)(c->ds_start + c->max_slots) * S * 4); }
+size_t msg_bytes(const ldpc_code* c, MsgKind kind, int S) {
+    return align16((size_t)c->m * c->D * S * (kind == kMsgF32 ? 4 : 2));
+}
+size_t lds_bytes(const ldpc_code* c, MsgKind kind, int S) {
+    return float_bytes(c, S) + msg_bytes(c, kind, S) + align16((size_t)3 * S * 4);
 }
 
-int pick_dmax(int d) {
-    static const int kDs[] = {4, 6, 7, 8, 12, 16, 24, 32};
-    for (int x : kDs)
-        if (d <= x) return x;
+int threads_for(const ldpc_code* c, int S) {
+    const int cap = max_threads_for_degree(c->D);
+    int t = ((S * c->H * c->max_group_visits + 63) / 64) * 64;
+    t = std::max(64, std::min(t, cap));
+    return t - t % (S * c->H);
+}
+
+// Frames per workgroup. One slot keeps the most independent workgroups per
+// CU (measured fastest on the n=2304 workloads); NDGSBP_SLOTS=2 packs two.
+int pick_slots(const ldpc_code* c, MsgKind kind) {
+    const char* env = getenv("NDGSBP_SLOTS");
+    if (env && atoi(env) == 2 && lds_bytes(c, kind, 2) <= c->max_lds) return 2;
+    return 1;
+}
+
+// Padded degree of the kernel variant for h lanes per CN.
+int pick_degree(int d, int h) {
+    static const int kD1[] = {4, 6, 7, 8, 12, 16, 24, 32};
+    static const int kD2[] = {4, 6, 8, 12, 16, 24, 32};
+    if (h == 1) {
+        for (int x : kD1)
+            if (d <= x) return x;
+    } else {
+        for (int x : kD2)
+            if (d <= x) return x;
+    }
     return -1;
+}
+
+// Lanes per CN visit: the choice that wastes the fewest lane-edge slots in
+// the CN phase (idle lanes of the last wave plus padding edges), two lanes
+// on a tie. NDGSBP_LANES_PER_CN (1 or 2) overrides.
+int pick_lanes(int maxd, int max_visits, int64_t max_edges) {
+    const char* env = getenv("NDGSBP_LANES_PER_CN");
+    if (env && (atoi(env) == 1 || atoi(env) == 2)) return atoi(env);
+    double best_eff = -1.0;
+    int best = 1;
+    for (int h : {2, 1}) {
+        const int D = pick_degree(maxd, h);
+        const int lanes = std::min(1024, ((h * max_visits + 63) / 64) * 64);
+        const double eff = (double)max_edges / ((double)lanes * (D / h));
+        if (eff > best_eff + 1e-9) {
+            best_eff = eff;
+            best = h;
+        }
+    }
+    return best;
 }
 
 }  // namespace
@@ -181,15 +225,30 @@ int ldpc_code_create(const ldpc_h_csr* H, const ldpc_grouping* grouping, int32_t
     c->max_cn_degree = maxd;
     c->max_vn_degree = n ? *std::max_element(vdeg.begin(), vdeg.end()) : 0;
 
-    // padded degree of the tables and kernel variant
-    c->D = pick_dmax(std::max(1, maxd));
+    // lanes per CN and padded degree of the tables and kernel variant
+    {
+        int max_visits = 0;
+        int64_t max_edges = 0;
+        for (const auto& grp : groups) {
+            int64_t ed = 0;
+            for (int32_t cn : grp) ed += H->row_ptr[cn + 1] - H->row_ptr[cn];
+            max_visits = std::max<int>(max_visits, (int)grp.size());
+            max_edges = std::max(max_edges, ed);
+        }
+        c->H = pick_lanes(std::max(1, maxd), max_visits, max_edges);
+    }
+    c->D = pick_degree(std::max(1, maxd), c->H);
     c->uniform = true;
     for (int i = 0; i < m; ++i)
         if (H->row_ptr[i + 1] - H->row_ptr[i] != c->D) c->uniform = false;
     const int D = c->D;
-    const int W = (2 * D + 3) / 4 * 4;  // words per visit record
+    const int LH = c->H, DH = D / LH;
+    const int W = (2 * DH + 3) / 4 * 4;  // words per half-record
+    const int SD = (D + 3) / 4 * 4;      // syndrome row stride
     // float index of the first delta slot: right after the posteriors
-    const int32_t ds_start = (int32_t)(align16((size_t)(n + 4) * 4) / 4);
+    // (n real, one scratch for padding edges, one zero for syndrome padding)
+    const int32_t ds_start = n + 2;
+    c->ds_start = ds_start;
 
     // visit, edge-word and fix-up tables
     std::vector<int32_t> vcn;
@@ -219,25 +278,26 @@ int ldpc_code_create(const ldpc_h_csr* H, const ldpc_grouping* grouping, int32_t
                 fix.push_back(make_uint2((uint32_t)v | ((uint32_t)cnt[v] << 16), (uint32_t)slots));
                 slots += cnt[v];
             }
-        if ((int64_t)ds_start + slots > 65535 || (int64_t)ds_start + slots > (1 << 20)) {
+        if ((int64_t)ds_start + slots > (1 << 20)) {
             delete c;
-            return fail(LDPC_EUNSUPPORTED, "posteriors plus delta slots exceed 16-bit LDS indices");
+            return fail(LDPC_EUNSUPPORTED, "too many delta slots in one group");
         }
         for (int32_t cn : grp) {
             const int32_t b = H->row_ptr[cn], d = H->row_ptr[cn + 1] - b;
             vcn.push_back(cn);
             const size_t rec = vw.size();
-            vw.resize(rec + W, 0u);
+            vw.resize(rec + (size_t)LH * W, 0u);
             for (int32_t k = 0; k < D; ++k) {
-                uint32_t src = (uint32_t)n * 4u, dst = (uint32_t)n * 4u;  // padding edge
+                uint32_t src = 4u * (uint32_t)n, dst = 4u * (uint32_t)n;  // padding edge
                 if (k < d) {
                     const int32_t v = H->col_idx[b + k];
                     const int32_t tgt = cnt[v] >= 2 ? ds_start + first_slot[v] + next_fill[v]++ : v;
-                    src = (uint32_t)v * 4u;
-                    dst = (uint32_t)tgt * 4u;
+                    src = 4u * (uint32_t)v;
+                    dst = 4u * (uint32_t)tgt;
                 }
-                vw[rec + k] = src;
-                vw[rec + D + k] = dst;
+                const size_t half = rec + (size_t)(k / DH) * W;
+                vw[half + k % DH] = src;
+                vw[half + DH + k % DH] = dst;
             }
             c->edge_updates += d;
         }
@@ -252,10 +312,10 @@ int ldpc_code_create(const ldpc_h_csr* H, const ldpc_grouping* grouping, int32_t
         visit_ptr.push_back((int32_t)vcn.size());
         fix_ptr.push_back((int32_t)fix.size());
     }
-    std::vector<uint16_t> syn_col((size_t)m * D, (uint16_t)(n + 1));
+    std::vector<uint32_t> syn_col((size_t)m * SD, 4u * (uint32_t)(n + 1));
     for (int i = 0; i < m; ++i)
         for (int32_t q = H->row_ptr[i]; q < H->row_ptr[i + 1]; ++q)
-            syn_col[(size_t)i * D + (q - H->row_ptr[i])] = (uint16_t)H->col_idx[q];
+            syn_col[(size_t)i * SD + (q - H->row_ptr[i])] = 4u * (uint32_t)H->col_idx[q];
 
     DeviceGuard guard(device);
     if (!guard.ok) {
@@ -269,11 +329,14 @@ int ldpc_code_create(const ldpc_h_csr* H, const ldpc_grouping* grouping, int32_t
     if (e == hipSuccess) e = upload(&c->dev.fix, fix);
     if (e == hipSuccess) e = upload(&c->dev.fix_ptr, fix_ptr);
     if (e == hipSuccess) e = upload(&c->dev.syn_col, syn_col);
+    if (e == hipSuccess) e = hipMalloc((void**)&c->dev.work, sizeof(uint32_t) * 2 * kWorkRing);
+    if (e == hipSuccess) e = hipMemset(c->dev.work, 0, sizeof(uint32_t) * 2 * kWorkRing);
     if (e == hipSuccess) {
         int v = 0;
         e = hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, device);
         c->max_lds = (size_t)v;
     }
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&c->num_cus, hipDeviceAttributeMultiprocessorCount, device);
     if (e != hipSuccess) {
         free_tables(c->dev);
         delete c;
@@ -307,8 +370,8 @@ int ldpc_code_query(ldpc_code_t c, ldpc_code_info* info) {
     info->max_cn_degree = c->max_cn_degree;
     info->max_vn_degree = c->max_vn_degree;
     info->device = c->device;
-    info->lds_bytes_fp32 = (int64_t)lds_bytes(c, kMsgF32);
-    info->lds_bytes_16 = (int64_t)lds_bytes(c, kMsgF16);
+    info->lds_bytes_fp32 = (int64_t)lds_bytes(c, kMsgF32, 1);
+    info->lds_bytes_16 = (int64_t)lds_bytes(c, kMsgF16, 1);
     return LDPC_OK;
 }
 
@@ -328,12 +391,21 @@ int ldpc_decode(ldpc_code_t c, const float* llr, int32_t num_frames, int32_t max
 
     DeviceGuard guard(c->device);
     if (!guard.ok) return fail(LDPC_EHIP, "cannot select the code's device");
-    const size_t lds = lds_bytes(c, kind);
-    if (lds > c->max_lds)
-        return fail(LDPC_EUNSUPPORTED, "one frame needs " + std::to_string(lds) + " B of LDS, device allows " +
-                                           std::to_string(c->max_lds));
-    int threads = ((c->max_group_visits + 63) / 64) * 64;
-    threads = std::min(1024, std::max(64, threads));
+    if (lds_bytes(c, kind, 1) > c->max_lds)
+        return fail(LDPC_EUNSUPPORTED, "one frame needs " + std::to_string(lds_bytes(c, kind, 1)) +
+                                           " B of LDS, device allows " + std::to_string(c->max_lds));
+    LaunchShape shape;
+    shape.slots = pick_slots(c, kind);
+    shape.lanes = c->H;
+    shape.threads = threads_for(c, shape.slots);
+    shape.lds_bytes = lds_bytes(c, kind, shape.slots);
+    int per_cu = 0;
+    hipError_t oe = decode_occupancy(kind, c->D, c->uniform, shape.slots, shape.lanes, shape.threads,
+                                     shape.lds_bytes, &per_cu);
+    if (oe != hipSuccess) return hip_fail(oe, "occupancy query");
+    if (per_cu < 1) return fail(LDPC_EUNSUPPORTED, "kernel variant cannot be resident");
+    const int64_t need = ((int64_t)num_frames + shape.slots - 1) / shape.slots;
+    shape.blocks = (int)std::min<int64_t>((int64_t)per_cu * c->num_cus, need);
 
     DecodeArgs a;
     a.vcn = c->dev.vcn;
@@ -347,19 +419,19 @@ int ldpc_decode(ldpc_code_t c, const float* llr, int32_t num_frames, int32_t max
     a.post = post;
     a.iters = iters;
     a.syn_ok = syn_ok;
+    a.work = c->dev.work + 2 * (c->next_work.fetch_add(1) % kWorkRing);
     a.n = c->n;
     a.m = c->m;
     a.G = c->G;
     a.max_iter = max_iter;
     a.early_stop = (flags & LDPC_FLAG_EARLY_STOP) ? 1 : 0;
     a.num_frames = num_frames;
-    a.ds_start = (int32_t)(p_bytes(c) / 4);
-    a.ds_start_b = (uint32_t)p_bytes(c);
-    a.dummy_b = (uint32_t)c->n * 4u;
-    a.l_offset = (int32_t)(p_bytes(c) + ds_bytes(c));
+    a.ds_start = c->ds_start;
+    a.l_offset = (int32_t)float_bytes(c, shape.slots);
+    a.sh_offset = (int32_t)(float_bytes(c, shape.slots) + msg_bytes(c, kind, shape.slots));
     a.ymin = (float)(kXMin * kLog2e);
     a.ymax = (float)(kXMax * kLog2e);
-    hipError_t e = launch_decode(a, kind, c->D, c->uniform, threads, lds, (hipStream_t)hip_stream);
+    hipError_t e = launch_decode(a, kind, c->D, c->uniform, shape, (hipStream_t)hip_stream);
     if (e != hipSuccess) return hip_fail(e, "decode launch");
     return LDPC_OK;
 }

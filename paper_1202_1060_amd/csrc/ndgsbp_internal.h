@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <atomic>
 #include <string>
 #include <vector>
 
@@ -24,26 +25,31 @@ constexpr double kLn2 = 0.6931471805599453;
 constexpr double kXMax = 30.0;
 constexpr double kXMin = 1.8715245937680347e-13;
 
-// Table layout (built by ldpc_code_create for the code's padded degree D,
-// the smallest kernel variant >= the largest CN degree):
+// Table layout (built by ldpc_code_create). H lanes share a CN (1 or 2);
+// D is the padded CN degree of the kernel variant (a multiple of H, at least
+// the largest degree) and DH = D / H the edges per lane:
 //   vcn[j]         CN of visit j (visits of group g: visit_ptr[g] ..
-//                  visit_ptr[g+1]); its message row in LDS is vcn[j] * D;
-//   vw[j*W .. ]    edge records of visit j, W = 2D rounded up to 4 words:
-//                  word k = LDS byte offset of the posterior edge k reads
-//                  (its VN), word D + k = LDS byte offset the lane writes
-//                  after the update: the VN's posterior when the VN has no
-//                  other edge in this group, else a delta slot (offset >=
-//                  ds_start_b) that the fix-up pass folds in. Padding edges
-//                  (k >= degree) read and write posterior n, a scratch
-//                  posterior nobody else reads.
+//                  visit_ptr[g+1]); its messages are row vcn[j] of L;
+//   vw             per visit j and lane h a half-record of W = 2 DH rounded
+//                  up to 4 words, at (j * H + h) * W: word k = 4 x posterior
+//                  index edge h*DH + k reads (its VN); word DH + k = 4 x
+//                  float index the lane writes after the update: the VN's
+//                  posterior when the VN has no other edge in this group,
+//                  else a delta slot (index >= ds_start) that the fix-up
+//                  pass folds in. Padding edges read and write posterior n,
+//                  a scratch posterior nobody else reads.
 //   fix[q]         fix-up entry of a group: x = VN | count << 16,
 //                  y = first delta slot (relative to ds_start); a VN's slots
 //                  are consecutive and are added in slot order.
-//   syn_col[c*D+k] VN ids of check c for the syndrome, padded with n + 1
-//                  (a posterior fixed at 0, i.e. hard bit 0).
-// LDS of one frame, in this order: posteriors P[n + 2] (floats) and two
-// int flags, delta slots
-// (floats, ds_start = first index), messages L[m * D] (FP32 or 16-bit).
+//   syn_col        check c at c * SD (SD = D rounded up to 4): 4 x the VN
+//                  ids of the check, padded with 4 x (n + 1) (a posterior
+//                  fixed at +0, i.e. hard bit 0).
+// LDS of a workgroup with S frame slots, elements interleaved by slot
+// (element e of slot s at e*S + s):
+//   floats [0, (ds_start + max_slots) * S): posteriors (n + 2 per slot,
+//     ds_start >= n + 2) then delta slots;
+//   at l_offset: messages L[(cn*D + k)*S + s] (FP32 or 16-bit);
+//   at sh_offset: int frame[S], int flag[2][S].
 
 struct DeviceTables {
     int32_t* vcn = nullptr;
@@ -51,7 +57,8 @@ struct DeviceTables {
     int32_t* visit_ptr = nullptr;  // G + 1
     uint2* fix = nullptr;
     int32_t* fix_ptr = nullptr;    // G + 1
-    uint16_t* syn_col = nullptr;   // m * D
+    uint32_t* syn_col = nullptr;   // m * SD
+    uint32_t* work = nullptr;      // kWorkRing pairs {next frame, finished workgroups}
 };
 
 struct DecodeArgs {
@@ -60,30 +67,44 @@ struct DecodeArgs {
     const int32_t* visit_ptr;
     const uint2* fix;
     const int32_t* fix_ptr;
-    const uint16_t* syn_col;
+    const uint32_t* syn_col;
     const float* llr;
     uint8_t* hard;
     float* post;
     int32_t* iters;
     uint8_t* syn_ok;
+    uint32_t* work;     // this launch's {next frame, finished workgroups}, zero at launch
     int32_t n, m, G;
     int32_t max_iter;
     int32_t early_stop;
     int32_t num_frames;
     int32_t ds_start;   // float index of the first delta slot
-    uint32_t ds_start_b;  // the same, in bytes
-    uint32_t dummy_b;   // byte offset of the scratch posterior n
     int32_t l_offset;   // byte offset of the message array
+    int32_t sh_offset;  // byte offset of the per-slot state
     float ymin, ymax;   // clamp bounds in log2 units
+};
+
+struct LaunchShape {
+    int slots;       // frames per workgroup
+    int lanes;       // lanes per CN visit (1 or 2)
+    int threads;     // workgroup size
+    int blocks;      // persistent workgroups
+    size_t lds_bytes;
 };
 
 enum MsgKind { kMsgF32 = 0, kMsgF16 = 1, kMsgBF16 = 2 };
 
 // Launch one decode; implemented next to the kernels.
-hipError_t launch_decode(const DecodeArgs& a, MsgKind kind, int dmax, bool uniform, int threads,
-                         size_t lds_bytes, hipStream_t stream);
+hipError_t launch_decode(const DecodeArgs& a, MsgKind kind, int dmax, bool uniform, const LaunchShape& shape,
+                         hipStream_t stream);
+// Resident workgroups per CU of a kernel variant.
+hipError_t decode_occupancy(MsgKind kind, int dmax, bool uniform, int slots, int lanes, int threads,
+                            size_t lds_bytes, int* blocks_per_cu);
+int max_threads_for_degree(int dmax);
 // Largest CN degree any kernel variant handles.
 constexpr int kMaxDegree = 32;
+// Work counters per code: decode calls in flight on one code at once, at most.
+constexpr int kWorkRing = 1024;
 
 }  // namespace ndgsbp
 
@@ -99,7 +120,11 @@ struct ldpc_code {
     int32_t max_group_visits;
     int32_t max_slots;
     int32_t D;        // padded CN degree of the tables (kernel variant)
+    int32_t H;        // lanes per CN visit
     bool uniform;     // every CN has degree exactly D
     size_t max_lds;   // LDS a workgroup may use on the code's device
+    int32_t num_cus;  // compute units of the code's device
+    int32_t ds_start; // float index of the first delta slot
+    std::atomic<uint32_t> next_work{0};  // ring position of the next decode call
     ndgsbp::DeviceTables dev;
 };

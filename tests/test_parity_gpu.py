@@ -186,3 +186,50 @@ def test_largest_code_that_fits_and_one_that_does_not():
     assert ei.value.code == nd.LDPC_EUNSUPPORTED
     bcode.close()
     print("lds per frame (fp32, 16-bit):", info["lds_bytes_fp32"], info["lds_bytes_16"])
+
+
+@pytest.mark.parametrize("recipe", ["sweep", "qc"])
+def test_slot_counts_give_identical_results(recipe, monkeypatch):
+    """One or two frames per workgroup: each frame's arithmetic is the same,
+    so the results must be bitwise identical."""
+    rec = W.SWEEP if recipe == "sweep" else W.PRECISION
+    code = W.CODES[rec["code"]]()
+    llr, _ = W.frames(rec, 1, num_frames=300)
+    dcode = nd.Code(code, windows=rec["windows"])
+    outs = []
+    for slots in ("1", "2"):
+        monkeypatch.setenv("NDGSBP_SLOTS", slots)
+        outs.append(gpu_decode(dcode, llr, rec["max_iter"], True))
+    dcode.close()
+    for o in outs[1:]:
+        for k in o:
+            assert np.array_equal(o[k], outs[0][k]), k
+
+
+def test_repeated_launches_reuse_work_counters():
+    """More decode calls than the work-counter ring holds, back to back on one
+    stream: every call must see a fresh counter."""
+    code = W.code_n96()
+    dcode = nd.Code(code, windows=(4, 2, 1))
+    llr, _ = make_frames(code.n, 37, 2.0, 0.5, seed=44)
+    first = gpu_decode(dcode, llr, 10, True)
+    x = torch.from_numpy(llr).to("cuda:0")
+    out = None
+    for _ in range(1100):
+        out = nd.decode(dcode, x, 10, early_stop=True)
+    torch.cuda.synchronize()
+    dcode.close()
+    for k in first:
+        assert np.array_equal(out[k].cpu().numpy(), first[k]), k
+
+
+@pytest.mark.parametrize("lanes", ["1", "2"])
+def test_lanes_per_check_node(lanes, monkeypatch):
+    """Both CN-phase mappings (one lane per CN visit, or two lanes sharing
+    it) meet the parity bar on the n=2304 workload and on the QC code."""
+    monkeypatch.setenv("NDGSBP_LANES_PER_CN", lanes)
+    for rec, snr in ((W.SWEEP, 2), (W.PRECISION, 0)):
+        code = W.CODES[rec["code"]]()
+        llr, _ = W.frames(rec, snr, num_frames=96, first_frame=500)
+        g, r = _run_both(code, rec["windows"], llr, rec["max_iter"], True)
+        print("lanes", lanes, rec["name"], compare(g, r))
