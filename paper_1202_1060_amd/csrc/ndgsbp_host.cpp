@@ -122,28 +122,17 @@ int expand_groups(const ldpc_grouping* g, int m, std::vector<std::vector<int32_t
     return LDPC_OK;
 }
 
-// LDS of a workgroup with S frame slots (layout in ndgsbp_internal.h).
-size_t float_bytes(const ldpc_code* c, int S) { return align16((size_t)(c->ds_start + c->max_slots) * S * 4); }
-size_t msg_bytes(const ldpc_code* c, MsgKind kind, int S) {
-    return align16((size_t)c->m * c->D * S * (kind == kMsgF32 ? 4 : 2));
+// LDS of a workgroup (layout in ndgsbp_internal.h).
+size_t float_bytes(const ldpc_code* c) { return align16((size_t)(c->ds_start + c->max_slots) * 4); }
+size_t msg_bytes(const ldpc_code* c, MsgKind kind) {
+    return align16((size_t)c->m * message_row_bytes(kind, c->D, c->H));
 }
-size_t lds_bytes(const ldpc_code* c, MsgKind kind, int S) {
-    return float_bytes(c, S) + msg_bytes(c, kind, S) + align16((size_t)3 * S * 4);
-}
+size_t lds_bytes(const ldpc_code* c, MsgKind kind) { return float_bytes(c) + msg_bytes(c, kind) + 16; }
 
-int threads_for(const ldpc_code* c, int S) {
+int threads_for(const ldpc_code* c) {
     const int cap = max_threads_for_degree(c->D);
-    int t = ((S * c->H * c->max_group_visits + 63) / 64) * 64;
-    t = std::max(64, std::min(t, cap));
-    return t - t % (S * c->H);
-}
-
-// Frames per workgroup. One slot keeps the most independent workgroups per
-// CU (measured fastest on the n=2304 workloads); NDGSBP_SLOTS=2 packs two.
-int pick_slots(const ldpc_code* c, MsgKind kind) {
-    const char* env = getenv("NDGSBP_SLOTS");
-    if (env && atoi(env) == 2 && lds_bytes(c, kind, 2) <= c->max_lds) return 2;
-    return 1;
+    int t = ((c->H * c->max_group_visits + 63) / 64) * 64;
+    return std::max(64, std::min(t, cap));
 }
 
 // Padded degree of the kernel variant for h lanes per CN.
@@ -370,8 +359,8 @@ int ldpc_code_query(ldpc_code_t c, ldpc_code_info* info) {
     info->max_cn_degree = c->max_cn_degree;
     info->max_vn_degree = c->max_vn_degree;
     info->device = c->device;
-    info->lds_bytes_fp32 = (int64_t)lds_bytes(c, kMsgF32, 1);
-    info->lds_bytes_16 = (int64_t)lds_bytes(c, kMsgF16, 1);
+    info->lds_bytes_fp32 = (int64_t)lds_bytes(c, kMsgF32);
+    info->lds_bytes_16 = (int64_t)lds_bytes(c, kMsgF16);
     return LDPC_OK;
 }
 
@@ -391,21 +380,18 @@ int ldpc_decode(ldpc_code_t c, const float* llr, int32_t num_frames, int32_t max
 
     DeviceGuard guard(c->device);
     if (!guard.ok) return fail(LDPC_EHIP, "cannot select the code's device");
-    if (lds_bytes(c, kind, 1) > c->max_lds)
-        return fail(LDPC_EUNSUPPORTED, "one frame needs " + std::to_string(lds_bytes(c, kind, 1)) +
+    if (lds_bytes(c, kind) > c->max_lds)
+        return fail(LDPC_EUNSUPPORTED, "one frame needs " + std::to_string(lds_bytes(c, kind)) +
                                            " B of LDS, device allows " + std::to_string(c->max_lds));
     LaunchShape shape;
-    shape.slots = pick_slots(c, kind);
     shape.lanes = c->H;
-    shape.threads = threads_for(c, shape.slots);
-    shape.lds_bytes = lds_bytes(c, kind, shape.slots);
+    shape.threads = threads_for(c);
+    shape.lds_bytes = lds_bytes(c, kind);
     int per_cu = 0;
-    hipError_t oe = decode_occupancy(kind, c->D, c->uniform, shape.slots, shape.lanes, shape.threads,
-                                     shape.lds_bytes, &per_cu);
+    hipError_t oe = decode_occupancy(kind, c->D, c->uniform, shape.lanes, shape.threads, shape.lds_bytes, &per_cu);
     if (oe != hipSuccess) return hip_fail(oe, "occupancy query");
     if (per_cu < 1) return fail(LDPC_EUNSUPPORTED, "kernel variant cannot be resident");
-    const int64_t need = ((int64_t)num_frames + shape.slots - 1) / shape.slots;
-    shape.blocks = (int)std::min<int64_t>((int64_t)per_cu * c->num_cus, need);
+    shape.blocks = (int)std::min<int64_t>((int64_t)per_cu * c->num_cus, num_frames);
 
     DecodeArgs a;
     a.vcn = c->dev.vcn;
@@ -426,9 +412,10 @@ int ldpc_decode(ldpc_code_t c, const float* llr, int32_t num_frames, int32_t max
     a.max_iter = max_iter;
     a.early_stop = (flags & LDPC_FLAG_EARLY_STOP) ? 1 : 0;
     a.num_frames = num_frames;
-    a.ds_start = c->ds_start;
-    a.l_offset = (int32_t)float_bytes(c, shape.slots);
-    a.sh_offset = (int32_t)(float_bytes(c, shape.slots) + msg_bytes(c, kind, shape.slots));
+    a.ds_start_b = 4u * (uint32_t)c->ds_start;
+    a.pad_b = 4u * (uint32_t)c->n;
+    a.l_offset = (int32_t)float_bytes(c);
+    a.sh_offset = (int32_t)(float_bytes(c) + msg_bytes(c, kind));
     a.ymin = (float)(kXMin * kLog2e);
     a.ymax = (float)(kXMax * kLog2e);
     hipError_t e = launch_decode(a, kind, c->D, c->uniform, shape, (hipStream_t)hip_stream);

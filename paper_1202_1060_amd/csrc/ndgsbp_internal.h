@@ -44,12 +44,12 @@ constexpr double kXMin = 1.8715245937680347e-13;
 //   syn_col        check c at c * SD (SD = D rounded up to 4): 4 x the VN
 //                  ids of the check, padded with 4 x (n + 1) (a posterior
 //                  fixed at +0, i.e. hard bit 0).
-// LDS of a workgroup with S frame slots, elements interleaved by slot
-// (element e of slot s at e*S + s):
-//   floats [0, (ds_start + max_slots) * S): posteriors (n + 2 per slot,
-//     ds_start >= n + 2) then delta slots;
-//   at l_offset: messages L[(cn*D + k)*S + s] (FP32 or 16-bit);
-//   at sh_offset: int frame[S], int flag[2][S].
+// LDS of a workgroup (one frame):
+//   floats [0, ds_start + max_slots): posteriors (n + 2, ds_start = n + 2)
+//     then delta slots;
+//   at l_offset: message rows, row (cn * H + h) of lane h of CN cn holding
+//     DH messages (FP32, or 16-bit with DH rounded up to even);
+//   at sh_offset: int frame, int flag[2].
 
 struct DeviceTables {
     int32_t* vcn = nullptr;
@@ -78,14 +78,14 @@ struct DecodeArgs {
     int32_t max_iter;
     int32_t early_stop;
     int32_t num_frames;
-    int32_t ds_start;   // float index of the first delta slot
-    int32_t l_offset;   // byte offset of the message array
-    int32_t sh_offset;  // byte offset of the per-slot state
+    uint32_t ds_start_b;  // byte offset of the first delta slot
+    uint32_t pad_b;     // byte offset of the scratch posterior n of padding edges
+    int32_t l_offset;   // byte offset of the message rows
+    int32_t sh_offset;  // byte offset of the frame index and flags
     float ymin, ymax;   // clamp bounds in log2 units
 };
 
 struct LaunchShape {
-    int slots;       // frames per workgroup
     int lanes;       // lanes per CN visit (1 or 2)
     int threads;     // workgroup size
     int blocks;      // persistent workgroups
@@ -98,9 +98,11 @@ enum MsgKind { kMsgF32 = 0, kMsgF16 = 1, kMsgBF16 = 2 };
 hipError_t launch_decode(const DecodeArgs& a, MsgKind kind, int dmax, bool uniform, const LaunchShape& shape,
                          hipStream_t stream);
 // Resident workgroups per CU of a kernel variant.
-hipError_t decode_occupancy(MsgKind kind, int dmax, bool uniform, int slots, int lanes, int threads,
-                            size_t lds_bytes, int* blocks_per_cu);
+hipError_t decode_occupancy(MsgKind kind, int dmax, bool uniform, int lanes, int threads, size_t lds_bytes,
+                            int* blocks_per_cu);
 int max_threads_for_degree(int dmax);
+// Bytes of the message rows of one CN.
+int message_row_bytes(MsgKind kind, int dmax, int lanes);
 // Largest CN degree any kernel variant handles.
 constexpr int kMaxDegree = 32;
 // Work counters per code: decode calls in flight on one code at once, at most.

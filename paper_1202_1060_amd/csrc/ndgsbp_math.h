@@ -41,41 +41,53 @@ __device__ __forceinline__ float exp2_hw(float x) { return __builtin_amdgcn_exp2
 __device__ __forceinline__ float log2_hw(float x) { return __builtin_amdgcn_logf(x); }
 __device__ __forceinline__ float rcp_hw(float x) { return __builtin_amdgcn_rcpf(x); }
 
-// Forward use (|VN->CN message| -> summand). Small results must keep their
-// relative accuracy (they are summed, and a small sum is mapped back to a
-// large message), so for v = 2^-y < 1/16 the ratio's logarithm is replaced by
-// the odd series 2 atanh(v) / ln 2 = (2/ln2)(v + v^3/3 + v^5/5 + v^7/7 + ...),
-// truncated after v^7 (relative error < 3e-11 there). Large results only need
-// absolute accuracy: a large summand drives the other outputs to ~0.
-__device__ __forceinline__ float psi_fwd(float y) {
-    const float v = exp2_hw(-y);
+// Forward use (|VN->CN message| -> summand), from v = 2^-y. Small results
+// must keep their relative accuracy (they are summed, and a small sum is
+// mapped back to a large message), so for v < kFwdSeriesMax the ratio's
+// logarithm is replaced by the odd series 2 atanh(v) / ln 2 =
+// (2/ln2)(v + v^3/3 + v^5/5 + v^7/7 + ...), truncated after v^7 (relative
+// error < 3e-11 there). Large results only need absolute accuracy: a large
+// summand drives the other outputs to ~0.
+constexpr float kFwdSeriesMax = 0.0625f;
+__device__ __forceinline__ float psi_fwd_series(float v) {
     const float w = v * v;
     const float c1 = 2.0f * kLog2eF, c3 = c1 / 3.0f, c5 = c1 / 5.0f, c7 = c1 / 7.0f;
-    const float ser = v * fmaf(w, fmaf(w, fmaf(w, c7, c5), c3), c1);
-    const float gen = log2_hw((1.0f + v) * rcp_hw(1.0f - v));
-    return v < 0.0625f ? ser : gen;
+    return v * fmaf(w, fmaf(w, fmaf(w, c7, c5), c3), c1);
+}
+__device__ __forceinline__ float psi_fwd_general(float v) { return log2_hw((1.0f + v) * rcp_hw(1.0f - v)); }
+__device__ __forceinline__ float psi_fwd(float y) {
+    const float v = exp2_hw(-y);
+    return v < kFwdSeriesMax ? psi_fwd_series(v) : psi_fwd_general(v);
 }
 
 // Inverse use (sum -> |CN->VN message|). A small sum gives a large message,
 // whose relative accuracy needs 1 - 2^-y without cancellation: for
-// z = y ln 2 < 1/4 it is taken from the Taylor series of 1 - e^-z up to z^6
-// (relative truncation error < 5e-8), written as a polynomial in y; above,
-// 1 - v loses at most ~2.7e-7. A large sum gives a small message, where
-// absolute accuracy suffices. The result is >= +0 (log2 of a ratio >= 1).
-__device__ __forceinline__ float psi_inv(float y) {
+// z = y ln 2 < 1/4 (y < kInvSeriesMax) it is taken from the Taylor series of
+// 1 - e^-z up to z^6 (relative truncation error < 5e-8), written as a
+// polynomial in y; above, 1 - v loses at most ~2.7e-7. A large sum gives a
+// small message, where absolute accuracy suffices. The result is >= +0
+// (log2 of a ratio >= 1).
+constexpr float kInvSeriesMax = (float)(0.25 / 0.6931471805599453);
+__device__ __forceinline__ float one_minus_exp2_neg(float y) {
     constexpr double l = 0.6931471805599453;
     constexpr float c1 = (float)l, c2 = (float)(-l * l / 2), c3 = (float)(l * l * l / 6),
                     c4 = (float)(-l * l * l * l / 24), c5 = (float)(l * l * l * l * l / 120),
                     c6 = (float)(-l * l * l * l * l * l / 720);
-    const float v = exp2_hw(-y);
     float p = fmaf(y, c6, c5);
     p = fmaf(y, p, c4);
     p = fmaf(y, p, c3);
     p = fmaf(y, p, c2);
     p = fmaf(y, p, c1);
-    const float den = y < (float)(0.25 / l) ? y * p : 1.0f - v;
-    return log2_hw((1.0f + v) * rcp_hw(den));
+    return y * p;
 }
+__device__ __forceinline__ float psi_inv_from(float v, float den) { return log2_hw((1.0f + v) * rcp_hw(den)); }
+__device__ __forceinline__ float psi_inv(float y) {
+    const float v = exp2_hw(-y);
+    return psi_inv_from(v, y < kInvSeriesMax ? one_minus_exp2_neg(y) : 1.0f - v);
+}
+
+// True when the predicate holds on any active lane of the wavefront.
+__device__ __forceinline__ bool wave_any(bool p) { return __builtin_amdgcn_ballot_w64(p) != 0; }
 
 __device__ __forceinline__ float clampf(float x, float lo, float hi) { return __builtin_amdgcn_fmed3f(x, lo, hi); }
 

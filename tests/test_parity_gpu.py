@@ -188,24 +188,6 @@ def test_largest_code_that_fits_and_one_that_does_not():
     print("lds per frame (fp32, 16-bit):", info["lds_bytes_fp32"], info["lds_bytes_16"])
 
 
-@pytest.mark.parametrize("recipe", ["sweep", "qc"])
-def test_slot_counts_give_identical_results(recipe, monkeypatch):
-    """One or two frames per workgroup: each frame's arithmetic is the same,
-    so the results must be bitwise identical."""
-    rec = W.SWEEP if recipe == "sweep" else W.PRECISION
-    code = W.CODES[rec["code"]]()
-    llr, _ = W.frames(rec, 1, num_frames=300)
-    dcode = nd.Code(code, windows=rec["windows"])
-    outs = []
-    for slots in ("1", "2"):
-        monkeypatch.setenv("NDGSBP_SLOTS", slots)
-        outs.append(gpu_decode(dcode, llr, rec["max_iter"], True))
-    dcode.close()
-    for o in outs[1:]:
-        for k in o:
-            assert np.array_equal(o[k], outs[0][k]), k
-
-
 def test_repeated_launches_reuse_work_counters():
     """More decode calls than the work-counter ring holds, back to back on one
     stream: every call must see a fresh counter."""
