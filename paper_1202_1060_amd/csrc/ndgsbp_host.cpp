@@ -418,6 +418,7 @@ int ldpc_decode(ldpc_code_t c, const float* llr, int32_t num_frames, int32_t max
     a.sh_offset = (int32_t)(float_bytes(c) + msg_bytes(c, kind));
     a.ymin = (float)(kXMin * kLog2e);
     a.ymax = (float)(kXMax * kLog2e);
+    a.cmin = (float)kXMin;
     hipError_t e = launch_decode(a, kind, c->D, c->uniform, shape, (hipStream_t)hip_stream);
     if (e != hipSuccess) return hip_fail(e, "decode launch");
     return LDPC_OK;

@@ -20,8 +20,11 @@ namespace ndgsbp {
 // linear and unaffected; posteriors are scaled back by ln 2 on store.
 constexpr double kLog2e = 1.4426950408889634;
 constexpr double kLn2 = 0.6931471805599453;
-// Magnitude clamp of the CN update, in nats: [phi(30), 30]. phi(30) =
-// 2 atanh(e^-30) = 2 e^-30 to double precision.
+// Magnitude clamp of the CN update, in nats: [phi(30), 30] at both phi inputs
+// of the sign-magnitude rule. phi(30) = 2 atanh(e^-30) = 2 e^-30 to double
+// precision. In complement form the clamp of the phi sum S to [phi(30), 30]
+// is a clamp of c = 1 - e^-S to [1 - e^-phi(30), 1 - e^-30]: the lower bound
+// is phi(30) to double precision, the upper bound rounds to 1 in FP32.
 constexpr double kXMax = 30.0;
 constexpr double kXMin = 1.8715245937680347e-13;
 
@@ -82,7 +85,8 @@ struct DecodeArgs {
     uint32_t pad_b;     // byte offset of the scratch posterior n of padding edges
     int32_t l_offset;   // byte offset of the message rows
     int32_t sh_offset;  // byte offset of the frame index and flags
-    float ymin, ymax;   // clamp bounds in log2 units
+    float ymin, ymax;   // clamp of |VN->CN message|, log2 units
+    float cmin;         // lower clamp of the complement 1 - prod tanh
 };
 
 struct LaunchShape {

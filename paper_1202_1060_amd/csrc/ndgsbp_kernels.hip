@@ -41,6 +41,11 @@ typedef __attribute__((address_space(3))) uint32_t lds_u32;
 __device__ __forceinline__ lds_float& lds_f32(uint32_t byte_off) { return *(lds_float*)(size_t)byte_off; }
 __device__ __forceinline__ lds_int& lds_i32(uint32_t byte_off) { return *(lds_int*)(size_t)byte_off; }
 
+// Reads of the code tables, which no kernel writes: through the constant
+// address space, so wavefront-uniform indices become scalar loads.
+typedef const __attribute__((address_space(4))) int32_t const_i32;
+__device__ __forceinline__ int32_t table_i32(const int32_t* base, int i) { return ((const_i32*)base)[i]; }
+
 // Message row of one lane: DH messages of its edges, stored in DP slots
 // (DP = DH for FP32; DH rounded up to even for 16-bit formats so that a row
 // is a whole number of dwords and moves with vector LDS instructions).
@@ -97,11 +102,15 @@ struct VisitRegs {
     uint32_t ta[DH];
 };
 
+// Visit records of a group start at the uniform address of visit j0; this
+// lane's record is `item` visits further, half h.
 template <int DH, int H>
-__device__ __forceinline__ void load_visit(const DecodeArgs& a, int j, int h, VisitRegs<DH>& r) {
+__device__ __forceinline__ void load_visit(const DecodeArgs& a, int j0, int item, int h, VisitRegs<DH>& r) {
     constexpr int W = VisitRegs<DH>::kWords;
-    r.cn = a.vcn[j];
-    const uint4* src = reinterpret_cast<const uint4*>(a.vw) + ((size_t)j * H + h) * (W / 4);
+    const unsigned char* cbase = reinterpret_cast<const unsigned char*>(a.vcn) + (size_t)j0 * 4;
+    const unsigned char* wbase = reinterpret_cast<const unsigned char*>(a.vw) + (size_t)j0 * (H * W * 4);
+    r.cn = *reinterpret_cast<const int32_t*>(cbase + (uint32_t)item * 4u);
+    const uint4* src = reinterpret_cast<const uint4*>(wbase + (uint32_t)(item * H + h) * (uint32_t)(W * 4));
     uint32_t w[W];
 #pragma unroll
     for (int q = 0; q < W / 4; ++q) {
@@ -124,16 +133,17 @@ __device__ __forceinline__ uint32_t pair_swap(uint32_t x) {
 }
 
 // One lane's share of a CN visit: eq. (1) for its edges, then the add-back.
-// With H = 2 the two lanes of a CN exchange their partial magnitude sums and
-// sign parities, so every exclusive sum is the lane's own prefix + suffix
-// plus the partner's total (all terms >= 0: no cancellation).
+// Per edge the lane forms eps = 1 - tanh(|x|/2) of its VN->CN message and
+// combines the eps of the other edges of the CN with (+) (ndgsbp_math.h) by
+// exclusive prefix and suffix; with H = 2 the two lanes of a CN exchange
+// their partial combinations and sign parities by DPP.
 // UNI: every CN has degree D, so no edge is padding.
 template <class M, int D, bool UNI, int H>
 __device__ __forceinline__ void cn_visit(const DecodeArgs& a, const VisitRegs<D / H>& r, uint32_t h) {
     constexpr int DH = D / H;
     using R = Row<M, DH>;
-    const uint32_t row = (uint32_t)a.l_offset + (uint32_t)(r.cn * H + (int)h) * (uint32_t)R::kBytes;
-    float t[DH], lo[DH], ps[DH], v[DH];
+    const uint32_t row = (uint32_t)a.l_offset + __umul24((uint32_t)(r.cn * H) + h, (uint32_t)R::kBytes);
+    float t[DH], lo[DH], e[DH];
     uint32_t tb[DH];
     uint32_t sall = 0;
     R::load(row, lo);
@@ -142,61 +152,38 @@ __device__ __forceinline__ void cn_visit(const DecodeArgs& a, const VisitRegs<D 
         t[k] = lds_f32(r.pa[k]) - lo[k];  // VN->CN message, eq. (2)
         // posteriors never hold -0.0, so the sign bit of t is the sign rule
         tb[k] = __float_as_uint(t[k]);
-        v[k] = exp2_hw(-clampf(fabsf(t[k]), a.ymin, a.ymax));
-        // both forms, then a select (no divergent branch per edge)
-        const float ser = psi_fwd_series(v[k]), gen = psi_fwd_general(v[k]);
-        ps[k] = v[k] < kFwdSeriesMax ? ser : gen;
-    }
-#pragma unroll
-    for (int k = 0; k < DH; ++k) {
+        e[k] = tanh_complement(exp2_hw(-clampf(fabsf(t[k]), a.ymin, a.ymax)));
         if (!UNI) {
             const bool real = r.pa[k] != a.pad_b;
-            ps[k] = real ? ps[k] : 0.0f;
+            e[k] = real ? e[k] : 0.0f;  // 0 is the identity of (+)
             tb[k] = real ? tb[k] : 0u;
         }
         sall ^= tb[k];
     }
-    // exclusive sums over N(m) \ n: prefix + suffix (+ the partner's total)
-    float pre[DH], s[DH];
-    if (DH > 1) pre[1] = ps[0];
+    // exclusive combination over N(m) \ n: prefix (+) suffix (+ the partner's)
+    float pre[DH], c[DH];
+    if (DH > 1) pre[1] = e[0];
 #pragma unroll
-    for (int k = 2; k < DH; ++k) pre[k] = pre[k - 1] + ps[k - 1];
+    for (int k = 2; k < DH; ++k) pre[k] = oplus(pre[k - 1], e[k - 1]);
     float suf;
     if (H == 2) {
-        const float mine = DH > 1 ? pre[DH - 1] + ps[DH - 1] : ps[0];
+        const float mine = DH > 1 ? oplus(pre[DH - 1], e[DH - 1]) : e[0];
         suf = __uint_as_float(pair_swap(__float_as_uint(mine)));
         sall ^= pair_swap(sall);
-        s[DH - 1] = DH > 1 ? pre[DH - 1] + suf : suf;
+        c[DH - 1] = DH > 1 ? oplus(pre[DH - 1], suf) : suf;
     } else {
         suf = 0.0f;
-        s[DH - 1] = DH > 1 ? pre[DH - 1] : 0.0f;
+        c[DH - 1] = DH > 1 ? pre[DH - 1] : 0.0f;
     }
 #pragma unroll
     for (int k = DH - 2; k >= 0; --k) {
-        suf = (H == 1 && k == DH - 2) ? ps[k + 1] : suf + ps[k + 1];
-        s[k] = k == 0 ? suf : pre[k] + suf;
-    }
-    // inverse phi; the series for 1 - 2^-y only where some lane needs it
-    float y2[DH], v2[DH], den[DH];
-    bool small = false;
-#pragma unroll
-    for (int k = 0; k < DH; ++k) {
-        y2[k] = clampf(s[k], a.ymin, a.ymax);
-        v2[k] = exp2_hw(-y2[k]);
-        den[k] = 1.0f - v2[k];
-        small |= y2[k] < kInvSeriesMax;
-    }
-    if (wave_any(small)) {
-#pragma unroll
-        for (int k = 0; k < DH; ++k) {
-            const float ser = one_minus_exp2_neg(y2[k]);
-            den[k] = y2[k] < kInvSeriesMax ? ser : den[k];
-        }
+        suf = (H == 1 && k == DH - 2) ? e[k + 1] : oplus(suf, e[k + 1]);
+        c[k] = k == 0 ? suf : oplus(pre[k], suf);
     }
     typename M::T st[DH];
 #pragma unroll
     for (int k = 0; k < DH; ++k) {
-        const float mag = psi_inv_from(v2[k], den[k]);
+        const float mag = magnitude_from_complement(clampf(c[k], a.cmin, 1.0f));
         const uint32_t out = __float_as_uint(mag) | ((sall ^ tb[k]) & 0x80000000u);
         st[k] = M::pack(__uint_as_float(out));
         const float ls = M::unpack(st[k]);
@@ -273,8 +260,8 @@ __global__ __launch_bounds__(MaxThreads<D>::value) void ndgsbp_kernel(DecodeArgs
     if (frame >= 0) init_frame<M, D, H>(a, frame, tid, nt);
     // the first visit of every lane is fetched one group ahead
     VisitRegs<DH> nxt;
-    bool have_nxt = vitem < a.visit_ptr[1];
-    if (have_nxt) load_visit<DH, H>(a, vitem, lh, nxt);
+    bool have_nxt = vitem < table_i32(a.visit_ptr, 1);
+    if (have_nxt) load_visit<DH, H>(a, 0, vitem, lh, nxt);
     __syncthreads();
 
     for (int step = 0; frame >= 0; ++step) {
@@ -282,17 +269,18 @@ __global__ __launch_bounds__(MaxThreads<D>::value) void ndgsbp_kernel(DecodeArgs
             const VisitRegs<DH> cur = nxt;
             const bool have_cur = have_nxt;
             const int gn = g + 1 == a.G ? 0 : g + 1;
-            const int jn = a.visit_ptr[gn] + vitem;
-            have_nxt = jn < a.visit_ptr[gn + 1];
-            if (have_nxt) load_visit<DH, H>(a, jn, lh, nxt);
+            const int jn0 = table_i32(a.visit_ptr, gn), jn1 = table_i32(a.visit_ptr, gn + 1);
+            have_nxt = vitem < jn1 - jn0;
+            if (have_nxt) load_visit<DH, H>(a, jn0, vitem, lh, nxt);
             if (have_cur) cn_visit<M, D, UNI, H>(a, cur, lh);
-            for (int j = a.visit_ptr[g] + vitem + nvitem; j < a.visit_ptr[g + 1]; j += nvitem) {
+            const int j0 = table_i32(a.visit_ptr, g), j1 = table_i32(a.visit_ptr, g + 1);
+            for (int item = vitem + nvitem; item < j1 - j0; item += nvitem) {
                 VisitRegs<DH> extra;
-                load_visit<DH, H>(a, j, lh, extra);
+                load_visit<DH, H>(a, j0, item, lh, extra);
                 cn_visit<M, D, UNI, H>(a, extra, lh);
             }
             __syncthreads();
-            const int q0 = a.fix_ptr[g], q1 = a.fix_ptr[g + 1];
+            const int q0 = table_i32(a.fix_ptr, g), q1 = table_i32(a.fix_ptr, g + 1);
             if (q1 > q0) {
                 for (int q = q0 + tid; q < q1; q += nt) {
                     const uint2 e = a.fix[q];

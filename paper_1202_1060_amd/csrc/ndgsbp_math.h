@@ -1,5 +1,5 @@
-// Device-side arithmetic of the NDGSBP CN update: message storage formats and
-// psi, the log2-unit form of phi(x) = -ln tanh(x/2) (Sec. II-C, eq. (1)).
+// Device-side arithmetic of the NDGSBP CN update (Sec. II-C, eq. (1)):
+// message storage formats and the complement-product form of the CN rule.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -35,59 +35,34 @@ struct MsgBF16 {
     static __device__ __forceinline__ float unpack(T v) { return __uint_as_float((uint32_t)v << 16); }
 };
 
-// --- psi(y) = log2((1 + 2^-y) / (1 - 2^-y)), the log2-unit form of phi ---------
+// --- eq. (1) in complement-product form ---------------------------------------
+//
+// With magnitudes in log2 units (y = |x| log2 e) and v = 2^-y = e^-|x|:
+//   tanh(|x|/2) = (1 - v)/(1 + v) = 1 - eps,   eps = 2v/(1 + v),
+// and eq. (1) for the edge to n reads |L_{m->n}| = 2 atanh(u) with
+// u = prod_{n' != n} (1 - eps_{n'}). The decoder never forms u: it carries
+// c = 1 - u, combining inputs with
+//   c (+) eps = 1 - (1 - c)(1 - eps) = c + eps - c*eps,
+// which adds non-negative terms when c and eps are small (the reliable,
+// large-message case where 1 - u would cancel), and returns
+//   |L| (log2 units) = log2((1 + u)/(1 - u)) = log2((2 - c)/c).
+// This is the same function as the sign-magnitude phi rule
+// phi(sum phi(|x|)), phi(x) = -ln tanh(x/2): sum phi = -ln u.
+// Where c is close to 1 (some input unreliable) the result is small and only
+// its absolute accuracy matters, which the rounding of c near 1 keeps.
 
 __device__ __forceinline__ float exp2_hw(float x) { return __builtin_amdgcn_exp2f(x); }
 __device__ __forceinline__ float log2_hw(float x) { return __builtin_amdgcn_logf(x); }
 __device__ __forceinline__ float rcp_hw(float x) { return __builtin_amdgcn_rcpf(x); }
 
-// Forward use (|VN->CN message| -> summand), from v = 2^-y. Small results
-// must keep their relative accuracy (they are summed, and a small sum is
-// mapped back to a large message), so for v < kFwdSeriesMax the ratio's
-// logarithm is replaced by the odd series 2 atanh(v) / ln 2 =
-// (2/ln2)(v + v^3/3 + v^5/5 + v^7/7 + ...), truncated after v^7 (relative
-// error < 3e-11 there). Large results only need absolute accuracy: a large
-// summand drives the other outputs to ~0.
-constexpr float kFwdSeriesMax = 0.0625f;
-__device__ __forceinline__ float psi_fwd_series(float v) {
-    const float w = v * v;
-    const float c1 = 2.0f * kLog2eF, c3 = c1 / 3.0f, c5 = c1 / 5.0f, c7 = c1 / 7.0f;
-    return v * fmaf(w, fmaf(w, fmaf(w, c7, c5), c3), c1);
-}
-__device__ __forceinline__ float psi_fwd_general(float v) { return log2_hw((1.0f + v) * rcp_hw(1.0f - v)); }
-__device__ __forceinline__ float psi_fwd(float y) {
-    const float v = exp2_hw(-y);
-    return v < kFwdSeriesMax ? psi_fwd_series(v) : psi_fwd_general(v);
-}
+// eps = 1 - tanh(|x|/2) from v = 2^-y (relative error a few ulp for all y)
+__device__ __forceinline__ float tanh_complement(float v) { return 2.0f * (v * rcp_hw(1.0f + v)); }
 
-// Inverse use (sum -> |CN->VN message|). A small sum gives a large message,
-// whose relative accuracy needs 1 - 2^-y without cancellation: for
-// z = y ln 2 < 1/4 (y < kInvSeriesMax) it is taken from the Taylor series of
-// 1 - e^-z up to z^6 (relative truncation error < 5e-8), written as a
-// polynomial in y; above, 1 - v loses at most ~2.7e-7. A large sum gives a
-// small message, where absolute accuracy suffices. The result is >= +0
-// (log2 of a ratio >= 1).
-constexpr float kInvSeriesMax = (float)(0.25 / 0.6931471805599453);
-__device__ __forceinline__ float one_minus_exp2_neg(float y) {
-    constexpr double l = 0.6931471805599453;
-    constexpr float c1 = (float)l, c2 = (float)(-l * l / 2), c3 = (float)(l * l * l / 6),
-                    c4 = (float)(-l * l * l * l / 24), c5 = (float)(l * l * l * l * l / 120),
-                    c6 = (float)(-l * l * l * l * l * l / 720);
-    float p = fmaf(y, c6, c5);
-    p = fmaf(y, p, c4);
-    p = fmaf(y, p, c3);
-    p = fmaf(y, p, c2);
-    p = fmaf(y, p, c1);
-    return y * p;
-}
-__device__ __forceinline__ float psi_inv_from(float v, float den) { return log2_hw((1.0f + v) * rcp_hw(den)); }
-__device__ __forceinline__ float psi_inv(float y) {
-    const float v = exp2_hw(-y);
-    return psi_inv_from(v, y < kInvSeriesMax ? one_minus_exp2_neg(y) : 1.0f - v);
-}
+// 1 - (1 - c)(1 - e) in one add and one fused multiply-add
+__device__ __forceinline__ float oplus(float c, float e) { return fmaf(-c, e, c + e); }
 
-// True when the predicate holds on any active lane of the wavefront.
-__device__ __forceinline__ bool wave_any(bool p) { return __builtin_amdgcn_ballot_w64(p) != 0; }
+// log2((2 - c)/c): the message magnitude (log2 units) for complement c
+__device__ __forceinline__ float magnitude_from_complement(float c) { return log2_hw((2.0f - c) * rcp_hw(c)); }
 
 __device__ __forceinline__ float clampf(float x, float lo, float hi) { return __builtin_amdgcn_fmed3f(x, lo, hi); }
 
