@@ -41,6 +41,22 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def measured_traffic(msg):
+    """HBM bytes per launch from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE
+    record, if it was taken on the kernel sources as they are now (else None)."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "traffic_n2304_sweep.json")
+    if msg != "fp32" or not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    h = hashlib.sha1()
+    for p in rec["kernel_sources"]:
+        h.update(open(os.path.join(ROOT, p), "rb").read())
+    if h.hexdigest() != rec["kernel_sources_sha1"]:
+        return None
+    return rec["fetch_bytes_per_launch"] + rec["write_bytes_per_launch"]
+
+
 def make_inputs(rec, frames_per_snr):
     from ldpcgen import workloads as W
     llrs, cws = [], []
@@ -166,7 +182,8 @@ def main():
         "kernel_ms": kern_ms,
         "fer": fer_table(iters, hard),
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_SLOTS_PER_S / 1e12,
-                     "unit": "T VALU-slots/s", "frac": achieved / PEAK_SLOTS_PER_S, "traffic": None},
+                     "unit": "T VALU-slots/s", "frac": achieved / PEAK_SLOTS_PER_S,
+                     "traffic": measured_traffic(args.msg)},
     }
     if not args.no_fixed:
         fwall, fk, _, _ = measure(max(1, args.steps // 2), False, args.msg)
