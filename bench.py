@@ -92,6 +92,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fixed", action="store_true", help="skip the fixed-iteration pass")
     ap.add_argument("--no-fp16", action="store_true", help="skip the FP16-message pass")
+    ap.add_argument("--lanes", type=int, default=0, choices=[0, 1, 2],
+                    help="lanes per CN visit for every message format (0: built-in choice)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device copy (for scaling HBM byte counters)")
     args = ap.parse_args()
@@ -124,6 +126,9 @@ def main():
     log(f"inputs: {llr_np.shape} in {time.perf_counter() - t0:.1f} s")
     F = llr_np.shape[0]
     dcode = nd.Code(code, windows=rec["windows"])
+    if args.lanes:
+        for m in ("fp32", "fp16", "bf16"):
+            dcode.tune(m, args.lanes)
     e_iter = dcode.info["edge_updates"]
     llr = torch.from_numpy(llr_np).to(dev)
     out = dict(hard=torch.empty((F, code.n), dtype=torch.uint8, device=dev),
@@ -176,7 +181,8 @@ def main():
                                "(wrap), Eb/N0 1.0-2.5 dB step 0.25 x 16384 frames, I_max 20, "
                                "syndrome stop",
                    "frames_per_step": F, "k_info": enc.k, "n": code.n, "max_iter": rec["max_iter"],
-                   "early_stop": True, "msg": args.msg},
+                   "early_stop": True, "msg": args.msg,
+                   "lanes_per_cn": dcode.info[f"lanes_{args.msg}"]},
         "edge_updates_per_s": edge_updates / (kern_ms * 1e-3),
         "mean_iters": float(iters.mean()),
         "kernel_ms": kern_ms,
@@ -196,6 +202,7 @@ def main():
         # the precision form: FP16-stored messages, FP32 arithmetic, same frames
         hwall, hk, hiters, hhard = measure(args.steps, True, "fp16")
         result["fp16_messages"] = {"gbit_s": bits / hwall / 1e9, "kernel_ms": hk,
+                                   "lanes_per_cn": dcode.info["lanes_fp16"],
                                    "mean_iters": float(hiters.mean()), "fer": fer_table(hiters, hhard)}
     if not args.no_cpu_baseline:
         import oracle

@@ -82,15 +82,19 @@ typedef struct {
     int32_t max_vn_degree;
     int32_t device;
     int64_t lds_bytes_fp32;  /* per-frame LDS of the FP32-message kernel      */
-    int64_t lds_bytes_16;    /* per-frame LDS of the FP16/BF16-message kernel */
+    int64_t lds_bytes_16;    /* per-frame LDS of the FP16-message kernel      */
+    int32_t lanes_fp32;      /* lanes per CN visit used with FP32 messages    */
+    int32_t lanes_fp16;      /* ... with FP16 messages                        */
+    int32_t lanes_bf16;      /* ... with BF16 messages                        */
 } ldpc_code_info;
 
 /* Validate H and the grouping, build the device tables and upload them to
- * `device`. On success *out owns them until ldpc_code_destroy. The handle
- * is immutable and may be used from any thread and stream.
+ * `device`. On success *out owns them until ldpc_code_destroy. Apart from
+ * ldpc_code_tune the handle is read-only and may be used from any thread and
+ * stream.
  * Errors: EINVAL (bad CSR, VN out of range, duplicate VN in a row, CN out
  * of range or repeated within a group, CN in no group, window longer than
- * m), EUNSUPPORTED (n > 65535, CN degree > 32), ENOMEM, EHIP. */
+ * m), EUNSUPPORTED (n > 65533, CN degree > 32), ENOMEM, EHIP. */
 int ldpc_code_create(const ldpc_h_csr* H, const ldpc_grouping* grouping, int32_t device,
                      ldpc_code_t* out);
 
@@ -99,6 +103,16 @@ int ldpc_code_create(const ldpc_h_csr* H, const ldpc_grouping* grouping, int32_t
 int ldpc_code_destroy(ldpc_code_t code);
 
 int ldpc_code_query(ldpc_code_t code, ldpc_code_info* info);
+
+/* Choose the CN-phase mapping of later decodes of `code` with the message
+ * format in msg_flags (0, LDPC_FLAG_MSG_FP16 or LDPC_FLAG_MSG_BF16): one lane
+ * per CN visit (1) or two lanes sharing it (2); 0 restores the built-in
+ * choice. For tuners: the mappings compute eq. (1) with the same operations
+ * in a different summation order, so results agree up to float rounding.
+ * Not synchronised with decodes in flight on other threads.
+ * Errors: EINVAL (bad flags or value), EUNSUPPORTED (no kernel variant
+ * with that mapping for the code's CN degree). */
+int ldpc_code_tune(ldpc_code_t code, uint32_t msg_flags, int32_t lanes_per_cn);
 
 /* Decode num_frames frames (Sec. II-C, Steps 2-4).
  *   llr    device, float [num_frames][n]: channel LLRs L_n = 2 y_n / sigma^2

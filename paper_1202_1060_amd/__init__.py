@@ -19,7 +19,7 @@ from ._native import (LdpcError, LDPC_OK, LDPC_EINVAL, LDPC_ENOMEM, LDPC_EHIP,
                       LDPC_FLAG_EARLY_STOP, LDPC_FLAG_MSG_FP16, LDPC_FLAG_MSG_BF16)
 
 __all__ = [
-    "Code", "ldpc_code_create", "ldpc_code_destroy", "ldpc_code_query", "ldpc_decode",
+    "Code", "ldpc_code_create", "ldpc_code_destroy", "ldpc_code_query", "ldpc_code_tune", "ldpc_decode",
     "ldpc_last_error", "decode", "LdpcError", "msg_flag",
     "LDPC_FLAG_EARLY_STOP", "LDPC_FLAG_MSG_FP16", "LDPC_FLAG_MSG_BF16",
 ]
@@ -71,6 +71,10 @@ def ldpc_code_query(handle) -> dict:
     return {k: getattr(info, k) for k, _ in info._fields_}
 
 
+def ldpc_code_tune(handle, msg_flags: int, lanes_per_cn: int) -> None:
+    _native.check(_native.load().ldpc_code_tune(ctypes.c_void_p(handle), int(msg_flags), int(lanes_per_cn)))
+
+
 def ldpc_decode(handle, llr_ptr, num_frames, max_iter, flags, hard_ptr, post_ptr, iters_ptr,
                 syn_ok_ptr, stream) -> None:
     """Raw entry point: device pointers as ints (0 for NULL), stream handle as int."""
@@ -95,6 +99,12 @@ class Code:
                                        windows=windows, groups=groups, device=device)
         self.info = ldpc_code_query(self.handle)
         self.device = device
+
+    def tune(self, msg: str, lanes_per_cn: int) -> None:
+        """Pick the CN-phase mapping (1 or 2 lanes per CN visit, 0 = default)
+        used by decodes with message format ``msg``."""
+        ldpc_code_tune(self.handle, msg_flag(msg), lanes_per_cn)
+        self.info = ldpc_code_query(self.handle)
 
     def close(self):
         if getattr(self, "handle", None):

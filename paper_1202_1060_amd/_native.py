@@ -23,8 +23,8 @@ LDPC_FLAG_EARLY_STOP = 0x1
 LDPC_FLAG_MSG_FP16 = 0x2
 LDPC_FLAG_MSG_BF16 = 0x4
 
-EXPORTS = ("ldpc_code_create", "ldpc_code_destroy", "ldpc_code_query", "ldpc_decode",
-           "ldpc_last_error")
+EXPORTS = ("ldpc_code_create", "ldpc_code_destroy", "ldpc_code_query", "ldpc_code_tune",
+           "ldpc_decode", "ldpc_last_error")
 
 _i32p = ctypes.POINTER(ctypes.c_int32)
 
@@ -45,7 +45,9 @@ class ldpc_code_info(ctypes.Structure):
                 ("num_groups", ctypes.c_int32), ("cn_visits", ctypes.c_int64),
                 ("edge_updates", ctypes.c_int64), ("max_cn_degree", ctypes.c_int32),
                 ("max_vn_degree", ctypes.c_int32), ("device", ctypes.c_int32),
-                ("lds_bytes_fp32", ctypes.c_int64), ("lds_bytes_16", ctypes.c_int64)]
+                ("lds_bytes_fp32", ctypes.c_int64), ("lds_bytes_16", ctypes.c_int64),
+                ("lanes_fp32", ctypes.c_int32), ("lanes_fp16", ctypes.c_int32),
+                ("lanes_bf16", ctypes.c_int32)]
 
 
 class LdpcError(RuntimeError):
@@ -75,6 +77,8 @@ def load() -> ctypes.CDLL:
     lib.ldpc_code_destroy.argtypes = [vp]
     lib.ldpc_code_query.restype = ctypes.c_int
     lib.ldpc_code_query.argtypes = [vp, ctypes.POINTER(ldpc_code_info)]
+    lib.ldpc_code_tune.restype = ctypes.c_int
+    lib.ldpc_code_tune.argtypes = [vp, ctypes.c_uint32, ctypes.c_int32]
     lib.ldpc_decode.restype = ctypes.c_int
     lib.ldpc_decode.argtypes = [vp, vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_uint32,
                                 vp, vp, vp, vp, vp]

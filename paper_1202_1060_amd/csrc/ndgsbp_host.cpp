@@ -54,15 +54,19 @@ hipError_t upload(T** dst, const std::vector<T>& src) {
     return e;
 }
 
-void free_tables(DeviceTables& t) {
+void free_tables(ldpc_code* c) {
+    DeviceTables& t = c->dev;
     (void)hipFree(t.vcn);
-    (void)hipFree(t.vw);
     (void)hipFree(t.visit_ptr);
     (void)hipFree(t.fix);
     (void)hipFree(t.fix_ptr);
-    (void)hipFree(t.syn_col);
     (void)hipFree(t.work);
     t = DeviceTables{};
+    for (Layout& l : c->lay) {
+        (void)hipFree(l.vw);
+        (void)hipFree(l.syn_col);
+        l = Layout{};
+    }
 }
 
 // Expands the grouping into explicit CN lists (validated).
@@ -124,14 +128,16 @@ int expand_groups(const ldpc_grouping* g, int m, std::vector<std::vector<int32_t
 
 // LDS of a workgroup (layout in ndgsbp_internal.h).
 size_t float_bytes(const ldpc_code* c) { return align16((size_t)(c->ds_start + c->max_slots) * 4); }
-size_t msg_bytes(const ldpc_code* c, MsgKind kind) {
-    return align16((size_t)c->m * message_row_bytes(kind, c->D, c->H));
+size_t msg_bytes(const ldpc_code* c, const Layout& l, MsgKind kind) {
+    return align16((size_t)c->m * message_row_bytes(kind, l.D, l.H));
 }
-size_t lds_bytes(const ldpc_code* c, MsgKind kind) { return float_bytes(c) + msg_bytes(c, kind) + 16; }
+size_t lds_bytes(const ldpc_code* c, const Layout& l, MsgKind kind) {
+    return float_bytes(c) + msg_bytes(c, l, kind) + 16;
+}
 
-int threads_for(const ldpc_code* c) {
-    const int cap = max_threads_for_degree(c->D);
-    int t = ((c->H * c->max_group_visits + 63) / 64) * 64;
+int threads_for(const ldpc_code* c, const Layout& l) {
+    const int cap = max_threads_for_degree(l.D);
+    int t = ((l.H * c->max_group_visits + 63) / 64) * 64;
     return std::max(64, std::min(t, cap));
 }
 
@@ -149,16 +155,15 @@ int pick_degree(int d, int h) {
     return -1;
 }
 
-// Lanes per CN visit: the choice that wastes the fewest lane-edge slots in
-// the CN phase (idle lanes of the last wave plus padding edges), two lanes
-// on a tie. NDGSBP_LANES_PER_CN (1 or 2) overrides.
-int pick_lanes(int maxd, int max_visits, int64_t max_edges) {
-    const char* env = getenv("NDGSBP_LANES_PER_CN");
-    if (env && (atoi(env) == 1 || atoi(env) == 2)) return atoi(env);
+// Lanes per CN visit for a message format: the mapping that wastes the fewest
+// lane-edge slots in the CN phase (idle lanes of the last wave plus padding
+// edges), two lanes on a tie; ldpc_code_tune overrides it.
+int pick_lanes(const ldpc_code* c, int max_visits, int64_t max_edges) {
     double best_eff = -1.0;
     int best = 1;
     for (int h : {2, 1}) {
-        const int D = pick_degree(maxd, h);
+        if (!c->lay[h - 1].valid) continue;
+        const int D = c->lay[h - 1].D;
         const int lanes = std::min(1024, ((h * max_visits + 63) / 64) * 64);
         const double eff = (double)max_edges / ((double)lanes * (D / h));
         if (eff > best_eff + 1e-9) {
@@ -167,6 +172,10 @@ int pick_lanes(int maxd, int max_visits, int64_t max_edges) {
         }
     }
     return best;
+}
+
+MsgKind msg_kind(uint32_t flags) {
+    return (flags & LDPC_FLAG_MSG_FP16) ? kMsgF16 : (flags & LDPC_FLAG_MSG_BF16) ? kMsgBF16 : kMsgF32;
 }
 
 }  // namespace
@@ -214,38 +223,20 @@ int ldpc_code_create(const ldpc_h_csr* H, const ldpc_grouping* grouping, int32_t
     c->max_cn_degree = maxd;
     c->max_vn_degree = n ? *std::max_element(vdeg.begin(), vdeg.end()) : 0;
 
-    // lanes per CN and padded degree of the tables and kernel variant
-    {
-        int max_visits = 0;
-        int64_t max_edges = 0;
-        for (const auto& grp : groups) {
-            int64_t ed = 0;
-            for (int32_t cn : grp) ed += H->row_ptr[cn + 1] - H->row_ptr[cn];
-            max_visits = std::max<int>(max_visits, (int)grp.size());
-            max_edges = std::max(max_edges, ed);
-        }
-        c->H = pick_lanes(std::max(1, maxd), max_visits, max_edges);
-    }
-    c->D = pick_degree(std::max(1, maxd), c->H);
-    c->uniform = true;
-    for (int i = 0; i < m; ++i)
-        if (H->row_ptr[i + 1] - H->row_ptr[i] != c->D) c->uniform = false;
-    const int D = c->D;
-    const int LH = c->H, DH = D / LH;
-    const int W = (2 * DH + 3) / 4 * 4;  // words per half-record
-    const int SD = (D + 3) / 4 * 4;      // syndrome row stride
     // float index of the first delta slot: right after the posteriors
     // (n real, one scratch for padding edges, one zero for syndrome padding)
     const int32_t ds_start = n + 2;
     c->ds_start = ds_start;
 
-    // visit, edge-word and fix-up tables
+    // visits, edge source/target indices and fix-up tables (mapping-free)
     std::vector<int32_t> vcn;
-    std::vector<uint32_t> vw;
+    std::vector<uint32_t> esrc, edst;  // per visit edge, in row order
+    std::vector<int32_t> vdeg_of(1, 0);  // prefix over visits of their degree
     std::vector<int32_t> visit_ptr(1, 0), fix_ptr(1, 0);
     std::vector<uint2> fix;
     std::vector<int32_t> cnt(n, 0), first_slot(n, -1), next_fill(n, 0);
     std::vector<int32_t> seen_order;
+    int64_t max_edges = 0;
     c->cn_visits = 0;
     c->edge_updates = 0;
     c->max_group_visits = 0;
@@ -271,40 +262,77 @@ int ldpc_code_create(const ldpc_h_csr* H, const ldpc_grouping* grouping, int32_t
             delete c;
             return fail(LDPC_EUNSUPPORTED, "too many delta slots in one group");
         }
+        int64_t edges = 0;
         for (int32_t cn : grp) {
             const int32_t b = H->row_ptr[cn], d = H->row_ptr[cn + 1] - b;
             vcn.push_back(cn);
-            const size_t rec = vw.size();
-            vw.resize(rec + (size_t)LH * W, 0u);
-            for (int32_t k = 0; k < D; ++k) {
-                uint32_t src = 4u * (uint32_t)n, dst = 4u * (uint32_t)n;  // padding edge
-                if (k < d) {
-                    const int32_t v = H->col_idx[b + k];
-                    const int32_t tgt = cnt[v] >= 2 ? ds_start + first_slot[v] + next_fill[v]++ : v;
-                    src = 4u * (uint32_t)v;
-                    dst = 4u * (uint32_t)tgt;
-                }
-                const size_t half = rec + (size_t)(k / DH) * W;
-                vw[half + k % DH] = src;
-                vw[half + DH + k % DH] = dst;
+            for (int32_t k = 0; k < d; ++k) {
+                const int32_t v = H->col_idx[b + k];
+                const int32_t tgt = cnt[v] >= 2 ? ds_start + first_slot[v] + next_fill[v]++ : v;
+                esrc.push_back((uint32_t)v);
+                edst.push_back((uint32_t)tgt);
             }
-            c->edge_updates += d;
+            vdeg_of.push_back(vdeg_of.back() + d);
+            edges += d;
         }
         for (int32_t v : seen_order) {
             cnt[v] = 0;
             first_slot[v] = -1;
             next_fill[v] = 0;
         }
+        c->edge_updates += edges;
+        max_edges = std::max(max_edges, edges);
         c->cn_visits += (int64_t)grp.size();
         c->max_group_visits = std::max<int32_t>(c->max_group_visits, (int32_t)grp.size());
         c->max_slots = std::max(c->max_slots, slots);
         visit_ptr.push_back((int32_t)vcn.size());
         fix_ptr.push_back((int32_t)fix.size());
     }
-    std::vector<uint32_t> syn_col((size_t)m * SD, 4u * (uint32_t)(n + 1));
-    for (int i = 0; i < m; ++i)
-        for (int32_t q = H->row_ptr[i]; q < H->row_ptr[i + 1]; ++q)
-            syn_col[(size_t)i * SD + (q - H->row_ptr[i])] = 4u * (uint32_t)H->col_idx[q];
+
+    // per-mapping tables: edge half-records padded to D, syndrome rows
+    std::vector<uint32_t> vw_h[2], syn_h[2];
+    for (int h = 1; h <= 2; ++h) {
+        Layout& l = c->lay[h - 1];
+        const int D = pick_degree(std::max(1, maxd), h);
+        if (D < 0 || D % h) continue;
+        l.valid = true;
+        l.H = h;
+        l.D = D;
+        l.uniform = true;
+        for (int i = 0; i < m; ++i)
+            if (H->row_ptr[i + 1] - H->row_ptr[i] != D) l.uniform = false;
+        const int DH = D / h;
+        const int W = (2 * DH + 3) / 4 * 4;  // words per half-record
+        std::vector<uint32_t>& vw = vw_h[h - 1];
+        vw.assign(vcn.size() * (size_t)h * W, 0u);
+        for (size_t j = 0; j < vcn.size(); ++j) {
+            const int32_t e0 = vdeg_of[j], d = vdeg_of[j + 1] - e0;
+            for (int k = 0; k < D; ++k) {
+                uint32_t src = 4u * (uint32_t)n, dst = 4u * (uint32_t)n;  // padding edge
+                if (k < d) {
+                    src = 4u * esrc[e0 + k];
+                    dst = 4u * edst[e0 + k];
+                }
+                const size_t half = (j * h + (size_t)(k / DH)) * W;
+                vw[half + k % DH] = src;
+                vw[half + DH + k % DH] = dst;
+            }
+        }
+        const int SD = (D + 3) / 4 * 4;  // syndrome row stride
+        std::vector<uint32_t>& syn = syn_h[h - 1];
+        syn.assign((size_t)m * SD, 4u * (uint32_t)(n + 1));
+        for (int i = 0; i < m; ++i)
+            for (int32_t q = H->row_ptr[i]; q < H->row_ptr[i + 1]; ++q)
+                syn[(size_t)i * SD + (q - H->row_ptr[i])] = 4u * (uint32_t)H->col_idx[q];
+    }
+    // FP32 messages: the slot-count choice. 16-bit messages: one lane per
+    // visit, which measured faster than two on the (3,6)-regular n=2304
+    // workload (12.0 against 11.2 Gbit/s) although it idles more lanes.
+    const int lanes0 = pick_lanes(c, c->max_group_visits, max_edges);
+    const int lanes16 = c->lay[0].valid ? 1 : lanes0;
+    c->lanes_for[kMsgF32] = c->lanes_default[kMsgF32] = lanes0;
+    c->lanes_for[kMsgF16] = c->lanes_default[kMsgF16] = lanes16;
+    c->lanes_for[kMsgBF16] = c->lanes_default[kMsgBF16] = lanes16;
 
     DeviceGuard guard(device);
     if (!guard.ok) {
@@ -313,11 +341,14 @@ int ldpc_code_create(const ldpc_h_csr* H, const ldpc_grouping* grouping, int32_t
     }
     hipError_t e = hipSuccess;
     if (e == hipSuccess) e = upload(&c->dev.vcn, vcn);
-    if (e == hipSuccess) e = upload(&c->dev.vw, vw);
     if (e == hipSuccess) e = upload(&c->dev.visit_ptr, visit_ptr);
     if (e == hipSuccess) e = upload(&c->dev.fix, fix);
     if (e == hipSuccess) e = upload(&c->dev.fix_ptr, fix_ptr);
-    if (e == hipSuccess) e = upload(&c->dev.syn_col, syn_col);
+    for (int h = 1; h <= 2 && e == hipSuccess; ++h) {
+        if (!c->lay[h - 1].valid) continue;
+        e = upload(&c->lay[h - 1].vw, vw_h[h - 1]);
+        if (e == hipSuccess) e = upload(&c->lay[h - 1].syn_col, syn_h[h - 1]);
+    }
     if (e == hipSuccess) e = hipMalloc((void**)&c->dev.work, sizeof(uint32_t) * 2 * kWorkRing);
     if (e == hipSuccess) e = hipMemset(c->dev.work, 0, sizeof(uint32_t) * 2 * kWorkRing);
     if (e == hipSuccess) {
@@ -327,7 +358,7 @@ int ldpc_code_create(const ldpc_h_csr* H, const ldpc_grouping* grouping, int32_t
     }
     if (e == hipSuccess) e = hipDeviceGetAttribute(&c->num_cus, hipDeviceAttributeMultiprocessorCount, device);
     if (e != hipSuccess) {
-        free_tables(c->dev);
+        free_tables(c);
         delete c;
         return e == hipErrorOutOfMemory ? fail(LDPC_ENOMEM, "device allocation failed")
                                         : hip_fail(e, "uploading code tables");
@@ -341,7 +372,7 @@ int ldpc_code_destroy(ldpc_code_t code) {
     if (!code) return LDPC_OK;
     {
         DeviceGuard guard(code->device);
-        free_tables(code->dev);
+        free_tables(code);
     }
     delete code;
     return LDPC_OK;
@@ -359,8 +390,28 @@ int ldpc_code_query(ldpc_code_t c, ldpc_code_info* info) {
     info->max_cn_degree = c->max_cn_degree;
     info->max_vn_degree = c->max_vn_degree;
     info->device = c->device;
-    info->lds_bytes_fp32 = (int64_t)lds_bytes(c, kMsgF32);
-    info->lds_bytes_16 = (int64_t)lds_bytes(c, kMsgF16);
+    info->lds_bytes_fp32 = (int64_t)lds_bytes(c, c->lay[c->lanes_for[kMsgF32] - 1], kMsgF32);
+    info->lds_bytes_16 = (int64_t)lds_bytes(c, c->lay[c->lanes_for[kMsgF16] - 1], kMsgF16);
+    info->lanes_fp32 = c->lanes_for[kMsgF32];
+    info->lanes_fp16 = c->lanes_for[kMsgF16];
+    info->lanes_bf16 = c->lanes_for[kMsgBF16];
+    return LDPC_OK;
+}
+
+int ldpc_code_tune(ldpc_code_t c, uint32_t msg_flags, int32_t lanes_per_cn) {
+    g_last_error.clear();
+    if (!c) return fail(LDPC_EINVAL, "code is NULL");
+    if (msg_flags & ~(LDPC_FLAG_MSG_FP16 | LDPC_FLAG_MSG_BF16)) return fail(LDPC_EINVAL, "msg_flags: message format bits only");
+    if ((msg_flags & LDPC_FLAG_MSG_FP16) && (msg_flags & LDPC_FLAG_MSG_BF16))
+        return fail(LDPC_EINVAL, "MSG_FP16 and MSG_BF16 are exclusive");
+    const MsgKind kind = msg_kind(msg_flags);
+    if (lanes_per_cn == 0) {
+        c->lanes_for[kind] = c->lanes_default[kind];
+        return LDPC_OK;
+    }
+    if (lanes_per_cn != 1 && lanes_per_cn != 2) return fail(LDPC_EINVAL, "lanes_per_cn must be 0, 1 or 2");
+    if (!c->lay[lanes_per_cn - 1].valid) return fail(LDPC_EUNSUPPORTED, "no kernel variant with that mapping");
+    c->lanes_for[kind] = lanes_per_cn;
     return LDPC_OK;
 }
 
@@ -376,30 +427,31 @@ int ldpc_decode(ldpc_code_t c, const float* llr, int32_t num_frames, int32_t max
         return fail(LDPC_EINVAL, "MSG_FP16 and MSG_BF16 are exclusive");
     if (num_frames == 0) return LDPC_OK;
     if (!llr || !hard || !iters) return fail(LDPC_EINVAL, "llr, hard and iters are required");
-    const MsgKind kind = (flags & LDPC_FLAG_MSG_FP16) ? kMsgF16 : (flags & LDPC_FLAG_MSG_BF16) ? kMsgBF16 : kMsgF32;
+    const MsgKind kind = msg_kind(flags);
+    const Layout& lay = c->lay[c->lanes_for[kind] - 1];
 
     DeviceGuard guard(c->device);
     if (!guard.ok) return fail(LDPC_EHIP, "cannot select the code's device");
-    if (lds_bytes(c, kind) > c->max_lds)
-        return fail(LDPC_EUNSUPPORTED, "one frame needs " + std::to_string(lds_bytes(c, kind)) +
+    if (lds_bytes(c, lay, kind) > c->max_lds)
+        return fail(LDPC_EUNSUPPORTED, "one frame needs " + std::to_string(lds_bytes(c, lay, kind)) +
                                            " B of LDS, device allows " + std::to_string(c->max_lds));
     LaunchShape shape;
-    shape.lanes = c->H;
-    shape.threads = threads_for(c);
-    shape.lds_bytes = lds_bytes(c, kind);
+    shape.lanes = lay.H;
+    shape.threads = threads_for(c, lay);
+    shape.lds_bytes = lds_bytes(c, lay, kind);
     int per_cu = 0;
-    hipError_t oe = decode_occupancy(kind, c->D, c->uniform, shape.lanes, shape.threads, shape.lds_bytes, &per_cu);
+    hipError_t oe = decode_occupancy(kind, lay.D, lay.uniform, shape.lanes, shape.threads, shape.lds_bytes, &per_cu);
     if (oe != hipSuccess) return hip_fail(oe, "occupancy query");
     if (per_cu < 1) return fail(LDPC_EUNSUPPORTED, "kernel variant cannot be resident");
     shape.blocks = (int)std::min<int64_t>((int64_t)per_cu * c->num_cus, num_frames);
 
     DecodeArgs a;
     a.vcn = c->dev.vcn;
-    a.vw = c->dev.vw;
+    a.vw = lay.vw;
     a.visit_ptr = c->dev.visit_ptr;
     a.fix = c->dev.fix;
     a.fix_ptr = c->dev.fix_ptr;
-    a.syn_col = c->dev.syn_col;
+    a.syn_col = lay.syn_col;
     a.llr = llr;
     a.hard = hard;
     a.post = post;
@@ -415,11 +467,11 @@ int ldpc_decode(ldpc_code_t c, const float* llr, int32_t num_frames, int32_t max
     a.ds_start_b = 4u * (uint32_t)c->ds_start;
     a.pad_b = 4u * (uint32_t)c->n;
     a.l_offset = (int32_t)float_bytes(c);
-    a.sh_offset = (int32_t)(float_bytes(c) + msg_bytes(c, kind));
+    a.sh_offset = (int32_t)(float_bytes(c) + msg_bytes(c, lay, kind));
     a.ymin = (float)(kXMin * kLog2e);
     a.ymax = (float)(kXMax * kLog2e);
     a.cmin = (float)kXMin;
-    hipError_t e = launch_decode(a, kind, c->D, c->uniform, shape, (hipStream_t)hip_stream);
+    hipError_t e = launch_decode(a, kind, lay.D, lay.uniform, shape, (hipStream_t)hip_stream);
     if (e != hipSuccess) return hip_fail(e, "decode launch");
     return LDPC_OK;
 }

@@ -56,12 +56,20 @@ constexpr double kXMin = 1.8715245937680347e-13;
 
 struct DeviceTables {
     int32_t* vcn = nullptr;
-    uint32_t* vw = nullptr;
     int32_t* visit_ptr = nullptr;  // G + 1
     uint2* fix = nullptr;
     int32_t* fix_ptr = nullptr;    // G + 1
-    uint32_t* syn_col = nullptr;   // m * SD
     uint32_t* work = nullptr;      // kWorkRing pairs {next frame, finished workgroups}
+};
+
+// The tables that depend on the CN-phase mapping (H lanes per CN visit).
+struct Layout {
+    bool valid = false;
+    int32_t H = 1;          // lanes per CN visit
+    int32_t D = 0;          // padded CN degree (kernel variant), a multiple of H
+    bool uniform = false;   // every CN has degree exactly D
+    uint32_t* vw = nullptr;       // edge half-records
+    uint32_t* syn_col = nullptr;  // m * SD
 };
 
 struct DecodeArgs {
@@ -125,9 +133,9 @@ struct ldpc_code {
     int32_t max_vn_degree;
     int32_t max_group_visits;
     int32_t max_slots;
-    int32_t D;        // padded CN degree of the tables (kernel variant)
-    int32_t H;        // lanes per CN visit
-    bool uniform;     // every CN has degree exactly D
+    ndgsbp::Layout lay[2];    // lay[H - 1]: tables for H lanes per CN visit
+    int32_t lanes_for[3];     // chosen H per message format (MsgKind)
+    int32_t lanes_default[3];
     size_t max_lds;   // LDS a workgroup may use on the code's device
     int32_t num_cus;  // compute units of the code's device
     int32_t ds_start; // float index of the first delta slot

@@ -19,7 +19,7 @@ def _declared():
 
 def test_header_declares_the_abi():
     assert _declared() == sorted(["ldpc_code_create", "ldpc_code_destroy", "ldpc_code_query",
-                                  "ldpc_decode", "ldpc_last_error"])
+                                  "ldpc_code_tune", "ldpc_decode", "ldpc_last_error"])
 
 
 def test_library_exports_every_declared_symbol():
@@ -98,6 +98,12 @@ def test_unsupported_sizes(nd):
 def test_decode_rejects_null_code(nd):
     with pytest.raises(nd.LdpcError) as ei:
         nd.ldpc_decode(0, 0, 1, 10, 0, 0, 0, 0, 0, 0)
+    assert ei.value.code == nd.LDPC_EINVAL
+
+
+def test_tune_rejects_null_code(nd):
+    with pytest.raises(nd.LdpcError) as ei:
+        nd.ldpc_code_tune(0, 0, 1)
     assert ei.value.code == nd.LDPC_EINVAL
 
 

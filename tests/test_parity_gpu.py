@@ -21,9 +21,11 @@ def _groups(code, windows):
     return oracle.windows(code.m, G, o, bool(wrap))
 
 
-def _run_both(code, windows, llr, max_iter, early_stop, msg="fp32", nthreads=0):
+def _run_both(code, windows, llr, max_iter, early_stop, msg="fp32", nthreads=0, lanes=0):
     dcode = nd.Code(code, windows=windows)
     try:
+        if lanes:
+            dcode.tune(msg, lanes)
         g = gpu_decode(dcode, llr, max_iter, early_stop, msg)
     finally:
         dcode.close()
@@ -205,13 +207,56 @@ def test_repeated_launches_reuse_work_counters():
         assert np.array_equal(out[k].cpu().numpy(), first[k]), k
 
 
-@pytest.mark.parametrize("lanes", ["1", "2"])
-def test_lanes_per_check_node(lanes, monkeypatch):
+def test_tune_arguments():
+    """ldpc_code_tune: bad values and unbuilt mappings are errors; 0
+    restores the default; each message format keeps its own choice."""
+    code = W.CODES["n96"]()
+    dcode = nd.Code(code, windows=(4, 2, 1))
+    try:
+        base = (dcode.info["lanes_fp32"], dcode.info["lanes_fp16"], dcode.info["lanes_bf16"])
+        for bad in (3, -1):
+            with pytest.raises(nd.LdpcError) as ei:
+                dcode.tune("fp32", bad)
+            assert ei.value.code == nd.LDPC_EINVAL
+        with pytest.raises(nd.LdpcError) as ei:
+            nd.ldpc_code_tune(dcode.handle, nd.LDPC_FLAG_MSG_FP16 | nd.LDPC_FLAG_MSG_BF16, 1)
+        assert ei.value.code == nd.LDPC_EINVAL
+        dcode.tune("bf16", 1)
+        assert dcode.info["lanes_bf16"] == 1
+        assert (dcode.info["lanes_fp32"], dcode.info["lanes_fp16"]) == base[:2]
+        dcode.tune("bf16", 0)
+        assert dcode.info["lanes_bf16"] == base[2]
+    finally:
+        dcode.close()
+    # degree 7: one lane runs the exact-degree variant, two lanes pad to 8
+    code = regular_code(84, 3, 7, seed=5)
+    llr, _ = make_frames(code.n, 64, 2.5, 4 / 7, seed=51)
+    for lanes in (1, 2):
+        g, r = _run_both(code, (5, 2, 1), llr, 12, True, lanes=lanes)
+        print("degree 7, lanes", lanes, compare(g, r))
+
+
+@pytest.mark.parametrize("lanes", [1, 2])
+@pytest.mark.parametrize("msg", ["fp32", "fp16"])
+def test_lanes_per_check_node(lanes, msg):
     """Both CN-phase mappings (one lane per CN visit, or two lanes sharing
-    it) meet the parity bar on the n=2304 workload and on the QC code."""
-    monkeypatch.setenv("NDGSBP_LANES_PER_CN", lanes)
+    it), chosen per message format, meet the parity bar on the n=2304
+    workload and on the QC code (FP32 messages: the two-tier bar; FP16:
+    the posterior error bound of the 16-bit formats)."""
     for rec, snr in ((W.SWEEP, 2), (W.PRECISION, 0)):
         code = W.CODES[rec["code"]]()
         llr, _ = W.frames(rec, snr, num_frames=96, first_frame=500)
-        g, r = _run_both(code, rec["windows"], llr, rec["max_iter"], True)
+        if msg == "fp16":
+            dcode = nd.Code(code, windows=rec["windows"])
+            try:
+                dcode.tune("fp16", lanes)
+                assert dcode.info["lanes_fp16"] == lanes
+                g = gpu_decode(dcode, llr, rec["max_iter"], True, "fp16")
+            finally:
+                dcode.close()
+            r = oracle.decode(code, _groups(code, rec["windows"]), llr, rec["max_iter"], True)
+            ok = r["syn_ok"].astype(bool)
+            assert np.mean(g["hard"][ok] != r["hard"][ok]) < 1e-3
+            continue
+        g, r = _run_both(code, rec["windows"], llr, rec["max_iter"], True, lanes=lanes)
         print("lanes", lanes, rec["name"], compare(g, r))
