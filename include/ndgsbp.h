@@ -130,6 +130,80 @@ int ldpc_decode(ldpc_code_t code, const float* llr, int32_t num_frames, int32_t 
                 uint32_t flags, uint8_t* hard, float* post, int32_t* iters, uint8_t* syn_ok,
                 void* hip_stream);
 
+/* ---- Batched decoding: many problems (codes, frame counts) per launch ----
+ *
+ * A batch decodes every frame of every problem with the schedule of
+ * ldpc_decode (Sec. II-C, Steps 2-4), each problem with its own code,
+ * grouping and iteration cap; the results of a problem equal those of
+ * ldpc_decode on it alone with the same message format and CN-lane mapping
+ * (bit for bit: the same arithmetic runs per frame). Problems are split into
+ * launch classes (kernel variant, optionally LDS size); each class is one
+ * persistent launch whose workgroups take frames of any of its problems from
+ * one work counter, and the classes run concurrently on forked streams. */
+typedef struct ldpc_batch* ldpc_batch_t;
+
+/* One problem. Buffers as in ldpc_decode (device memory of the code's
+ * device, [num_frames][n] frame-major); num_frames may be 0. */
+typedef struct {
+    ldpc_code_t code;
+    const float* llr;
+    int32_t num_frames;
+    int32_t max_iter;
+    uint8_t* hard;
+    float* post;     /* or NULL */
+    int32_t* iters;
+    uint8_t* syn_ok; /* or NULL */
+} ldpc_problem;
+
+/* Launch choices of a batch (the autotuner's knobs). */
+typedef struct {
+    int32_t lanes_per_cn;  /* 0: each code's mapping for the message format
+                              (ldpc_code_tune); 1 or 2: that mapping for all */
+    int32_t split_by_size; /* nonzero: one launch per power-of-two LDS size
+                              within a kernel variant (workgroups sized for
+                              their problems); 0: one launch per variant    */
+    int32_t max_threads;   /* workgroup size cap, multiple of 64, <= 1024;
+                              0: the size that gives every CN visit of the
+                              largest group its own lanes                   */
+    int32_t streams;       /* launch classes run on up to this many streams
+                              at once (1..8; 0 = 1)                          */
+} ldpc_batch_options;
+
+typedef struct {
+    int32_t num_launches;
+    int32_t num_problems;
+    int32_t num_streams;
+    int64_t total_frames;
+} ldpc_batch_info;
+
+/* Validate the problems, form the launch classes and upload the problem
+ * table to the codes' device. Pointers in `probs` are copied: the codes and
+ * buffers must stay valid while the batch is launched; `probs` itself is
+ * read during the call only. opt NULL = {0, 1, 0, 4}. flags as in
+ * ldpc_decode, for every problem. Synchronous.
+ * Errors: EINVAL (NULL code or required buffer, negative frames, max_iter
+ * < 1, codes on different devices, bad flags or options), EUNSUPPORTED (a
+ * code beyond every kernel variant, more than 2^31 - 1 frames in a class),
+ * ENOMEM, EHIP. */
+int ldpc_batch_create(const ldpc_problem* probs, int32_t count, uint32_t flags,
+                      const ldpc_batch_options* opt, ldpc_batch_t* out);
+
+/* Enqueue the batch on hip_stream (and on the batch's own streams, forked
+ * from and joined back into hip_stream): asynchronous, no allocation, no
+ * host synchronisation and no memset, so it may be captured into a HIP
+ * graph. Launches of one batch must not overlap in time (they share its
+ * work counters): keep them on one stream or otherwise ordered. */
+int ldpc_batch_launch(ldpc_batch_t batch, void* hip_stream);
+
+int ldpc_batch_query(ldpc_batch_t batch, ldpc_batch_info* info);
+
+/* The caller guarantees that no enqueued launch still uses the batch. */
+int ldpc_batch_destroy(ldpc_batch_t batch);
+
+/* One-shot form: create with default options, launch on hip_stream, wait
+ * for hip_stream to finish, destroy. Returns after the decode is done. */
+int ldpc_decode_batched(const ldpc_problem* probs, int32_t count, uint32_t flags, void* hip_stream);
+
 /* Message of the last failed call on this thread ("" if none). */
 const char* ldpc_last_error(void);
 

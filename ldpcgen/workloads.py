@@ -47,6 +47,28 @@ CODES = {
     "qc2304": lambda: code_qc(2304, "1/2", 1002),
 }
 
+# QC codes of the batched workload: one per (length, rate), seeds 1003..1014
+BATCH_N = (576, 1152, 2304, 4608)
+BATCH_RATES = ("1/2", "2/3", "3/4")
+
+
+def qc_key(n: int, rate: str) -> str:
+    return f"qc{n}r{rate.replace('/', '_')}"
+
+
+for _i, (_n, _r) in enumerate((n, r) for n in BATCH_N for r in BATCH_RATES):
+    CODES[qc_key(_n, _r)] = functools.partial(code_qc, _n, _r, 1003 + _i)
+
+# resident codes of the serving workload, seeds 1020..1022
+SERVE_CODES = ((648, "5/6"), (1944, "1/2"), (8064, "1/2"))
+for _i, (_n, _r) in enumerate(SERVE_CODES):
+    CODES[qc_key(_n, _r)] = functools.partial(code_qc, _n, _r, 1020 + _i)
+
+
+def base_rows(rate: str) -> int:
+    from .codes import QC_PROFILES
+    return QC_PROFILES[rate]["mb"]
+
 # workload recipes
 SMALL = dict(name="ndgsbp-n96-w4o2", code="n96", windows=(4, 2, 1), max_iter=10,
              early_stop=False, ebn0=[2.0], frames=200, all_zero=True, seed=2000)
@@ -57,6 +79,73 @@ SWEEP_FLOODING = dict(SWEEP, name="flooding-n2304", windows=(1, 0, 1))
 SWEEP_GSBP = dict(SWEEP, name="gsbp-n2304-w8", windows=(8, 0, 1))
 PRECISION = dict(name="ndgsbp-qc2304-w12o24", code="qc2304", windows=(12, 24, 1), max_iter=15,
                  early_stop=True, ebn0=[1.5, 2.0], frames=65536, all_zero=False, seed=2200)
+
+
+# Batched decoding: 256 problems, each a QC code of length in BATCH_N and
+# rate in BATCH_RATES (z = n/24), 64..1024 frames (log-uniform), Eb/N0 in
+# [1, 3] dB, 6..16 CN windows with overlap z/4 (wrap), FP16 messages,
+# 20 iterations, syndrome stop.
+BATCH = dict(name="batched-qc-mixed-256", problems=256, frames=(64, 1024), ebn0=(1.0, 3.0),
+             groups=(6, 16), max_iter=20, early_stop=True, msg="fp16", seed=2300)
+
+# Serving: requests over the three SERVE_CODES (one base row per window,
+# overlap floor(z/4), wrap), 1..512 frames (geometric, mean 32), Eb/N0 in
+# [1.5, 3.5] dB, Poisson arrivals, FP16 messages, 20 iterations, syndrome stop.
+SERVE = dict(name="serving-qc-3codes", mean_frames=32, max_frames=512, ebn0=(1.5, 3.5),
+             max_iter=20, early_stop=True, msg="fp16", seed=2400)
+
+
+def _philox(*key):
+    return np.random.Generator(np.random.Philox(np.random.SeedSequence([int(k) for k in key])))
+
+
+def batch_problems(recipe: dict = BATCH, count: int | None = None):
+    """The problem list of the batched workload (no frames yet): dicts with
+    code key, n, rate, windows (G, o, 1), frames, Eb/N0 and frame seed."""
+    rng = _philox(recipe["seed"], 0)
+    out = []
+    lo, hi = recipe["frames"]
+    for i in range(recipe["problems"] if count is None else count):
+        n = int(BATCH_N[rng.integers(len(BATCH_N))])
+        rate = BATCH_RATES[rng.integers(len(BATCH_RATES))]
+        z = n // 24
+        G = int(rng.integers(recipe["groups"][0], recipe["groups"][1] + 1))
+        F = int(round(float(np.exp(rng.uniform(np.log(lo), np.log(hi))))))
+        eb = float(rng.uniform(*recipe["ebn0"]))
+        out.append(dict(index=i, code=qc_key(n, rate), n=n, rate=rate, windows=(G, z // 4, 1),
+                        frames=F, ebn0=eb, max_iter=recipe["max_iter"],
+                        seed=recipe["seed"] * 1000 + 1 + i))
+    return out
+
+
+def serve_windows(n: int, rate: str):
+    """One base row per window, overlap floor(z/4), wrap."""
+    return (base_rows(rate), (n // 24) // 4, 1)
+
+
+def serve_requests(recipe: dict = SERVE, count: int = 256, rate_per_s: float = 1000.0):
+    """Request stream of the serving workload: dicts with arrival time (s,
+    Poisson at ``rate_per_s``), code key, frames, Eb/N0 and frame seed."""
+    rng = _philox(recipe["seed"], 0)
+    t = 0.0
+    out = []
+    p = 1.0 / recipe["mean_frames"]
+    for i in range(count):
+        t += float(rng.exponential(1.0 / rate_per_s))
+        n, rate = SERVE_CODES[rng.integers(len(SERVE_CODES))]
+        F = int(min(recipe["max_frames"], rng.geometric(p)))
+        eb = float(rng.uniform(*recipe["ebn0"]))
+        out.append(dict(index=i, arrival=t, code=qc_key(n, rate), n=n, rate=rate,
+                        windows=serve_windows(n, rate), frames=F, ebn0=eb,
+                        max_iter=recipe["max_iter"], seed=recipe["seed"] * 1000 + 1 + i))
+    return out
+
+
+def problem_frames(prob: dict, num_frames: int | None = None):
+    """LLRs and codewords of a batched problem or a serving request."""
+    enc = encoder_for(prob["code"])
+    nf = prob["frames"] if num_frames is None else num_frames
+    return make_frames(prob["n"], nf, prob["ebn0"], enc.rate, prob["seed"], encoder=enc)
 
 
 def frames(recipe: dict, snr_index: int, num_frames: int | None = None, first_frame: int = 0):

@@ -20,6 +20,8 @@ from ._native import (LdpcError, LDPC_OK, LDPC_EINVAL, LDPC_ENOMEM, LDPC_EHIP,
 
 __all__ = [
     "Code", "ldpc_code_create", "ldpc_code_destroy", "ldpc_code_query", "ldpc_code_tune", "ldpc_decode",
+    "ldpc_batch_create", "ldpc_batch_launch", "ldpc_batch_query", "ldpc_batch_destroy",
+    "ldpc_decode_batched", "Problem", "Batch", "BatchOptions", "decode_batched", "new_outputs",
     "ldpc_last_error", "decode", "LdpcError", "msg_flag",
     "LDPC_FLAG_EARLY_STOP", "LDPC_FLAG_MSG_FP16", "LDPC_FLAG_MSG_BF16",
 ]
@@ -142,3 +144,136 @@ def decode(code: Code, llr: torch.Tensor, max_iter: int, *, early_stop: bool = T
                 out["syn_ok"].data_ptr() if out.get("syn_ok") is not None else 0,
                 s.cuda_stream)
     return out
+
+
+# ---- batched decoding ------------------------------------------------------
+
+class BatchOptions:
+    """Launch choices of a batch (ldpc_batch_options). Defaults: each code's
+    CN-lane mapping, one launch per LDS size class, workgroups sized for the
+    largest group, four streams."""
+
+    __slots__ = ("lanes_per_cn", "split_by_size", "max_threads", "streams")
+
+    def __init__(self, lanes_per_cn=0, split_by_size=1, max_threads=0, streams=4):
+        self.lanes_per_cn = int(lanes_per_cn)
+        self.split_by_size = int(split_by_size)
+        self.max_threads = int(max_threads)
+        self.streams = int(streams)
+
+    def as_tuple(self):
+        return (self.lanes_per_cn, self.split_by_size, self.max_threads, self.streams)
+
+    @classmethod
+    def from_tuple(cls, t):
+        return cls(*t)
+
+    def __repr__(self):
+        return "BatchOptions(lanes_per_cn=%d, split_by_size=%d, max_threads=%d, streams=%d)" % self.as_tuple()
+
+    def _c(self):
+        return _native.ldpc_batch_options(*self.as_tuple())
+
+
+def new_outputs(F: int, n: int, device, want_post=True, want_syn=True) -> dict:
+    return dict(hard=torch.empty((F, n), dtype=torch.uint8, device=device),
+                post=torch.empty((F, n), dtype=torch.float32, device=device) if want_post else None,
+                iters=torch.empty((F,), dtype=torch.int32, device=device),
+                syn_ok=torch.empty((F,), dtype=torch.uint8, device=device) if want_syn else None)
+
+
+class Problem:
+    """One problem of a batch: a Code, a (F, n) float32 device tensor of
+    channel LLRs, an iteration cap and the output tensors (allocated here
+    unless given)."""
+
+    def __init__(self, code: Code, llr: torch.Tensor, max_iter: int, *, out=None, want_post=True,
+                 want_syn=True):
+        if llr.dtype != torch.float32 or llr.dim() != 2 or llr.shape[1] != code.n:
+            raise ValueError("llr must be a (F, n) float32 tensor")
+        if not llr.is_cuda or not llr.is_contiguous():
+            raise ValueError("llr must be a contiguous device tensor")
+        self.code, self.llr, self.max_iter = code, llr, int(max_iter)
+        self.out = out if out is not None else new_outputs(llr.shape[0], code.n, llr.device, want_post, want_syn)
+
+    def _c(self):
+        o = self.out
+        return _native.ldpc_problem(self.code.handle, self.llr.data_ptr(), int(self.llr.shape[0]),
+                                    self.max_iter, o["hard"].data_ptr(),
+                                    o["post"].data_ptr() if o.get("post") is not None else None,
+                                    o["iters"].data_ptr(),
+                                    o["syn_ok"].data_ptr() if o.get("syn_ok") is not None else None)
+
+
+def _problem_array(problems):
+    arr = (_native.ldpc_problem * max(1, len(problems)))()
+    for i, p in enumerate(problems):
+        arr[i] = p._c()
+    return arr
+
+
+def ldpc_batch_create(problems, flags: int, options: BatchOptions | None = None):
+    arr = _problem_array(problems)
+    out = ctypes.c_void_p()
+    opt = options._c() if options is not None else None
+    _native.check(_native.load().ldpc_batch_create(arr, len(problems), int(flags),
+                                                   ctypes.byref(opt) if opt is not None else None,
+                                                   ctypes.byref(out)))
+    return out.value
+
+
+def ldpc_batch_launch(handle, stream) -> None:
+    _native.check(_native.load().ldpc_batch_launch(ctypes.c_void_p(handle), ctypes.c_void_p(stream or None)))
+
+
+def ldpc_batch_query(handle) -> dict:
+    info = _native.ldpc_batch_info()
+    _native.check(_native.load().ldpc_batch_query(ctypes.c_void_p(handle), ctypes.byref(info)))
+    return {k: getattr(info, k) for k, _ in info._fields_}
+
+
+def ldpc_batch_destroy(handle) -> None:
+    _native.check(_native.load().ldpc_batch_destroy(ctypes.c_void_p(handle)))
+
+
+def ldpc_decode_batched(problems, flags: int, stream) -> None:
+    arr = _problem_array(problems)
+    _native.check(_native.load().ldpc_decode_batched(arr, len(problems), int(flags),
+                                                     ctypes.c_void_p(stream or None)))
+
+
+class Batch:
+    """A batch plan (ldpc_batch_*): created once, launched any number of
+    times (also inside a CUDA/HIP graph capture), each launch decoding every
+    problem's current LLR tensor into its output tensors."""
+
+    def __init__(self, problems, *, msg="fp16", early_stop=True, options: BatchOptions | None = None):
+        self.problems = list(problems)
+        self.flags = msg_flag(msg) | (LDPC_FLAG_EARLY_STOP if early_stop else 0)
+        self.handle = ldpc_batch_create(self.problems, self.flags, options)
+        self.info = ldpc_batch_query(self.handle)
+
+    def launch(self, stream=None):
+        dev = self.problems[0].llr.device if self.problems else torch.device("cuda", 0)
+        s = stream if stream is not None else torch.cuda.current_stream(dev)
+        ldpc_batch_launch(self.handle, s.cuda_stream)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            ldpc_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def decode_batched(problems, *, msg="fp16", early_stop=True, stream=None):
+    """One-shot batched decode (ldpc_decode_batched): returns when done."""
+    flags = msg_flag(msg) | (LDPC_FLAG_EARLY_STOP if early_stop else 0)
+    dev = problems[0].llr.device if problems else torch.device("cuda", 0)
+    s = stream if stream is not None else torch.cuda.current_stream(dev)
+    ldpc_decode_batched(problems, flags, s.cuda_stream)
+    return [p.out for p in problems]

@@ -24,7 +24,8 @@ LDPC_FLAG_MSG_FP16 = 0x2
 LDPC_FLAG_MSG_BF16 = 0x4
 
 EXPORTS = ("ldpc_code_create", "ldpc_code_destroy", "ldpc_code_query", "ldpc_code_tune",
-           "ldpc_decode", "ldpc_last_error")
+           "ldpc_decode", "ldpc_batch_create", "ldpc_batch_launch", "ldpc_batch_query",
+           "ldpc_batch_destroy", "ldpc_decode_batched", "ldpc_last_error")
 
 _i32p = ctypes.POINTER(ctypes.c_int32)
 
@@ -48,6 +49,22 @@ class ldpc_code_info(ctypes.Structure):
                 ("lds_bytes_fp32", ctypes.c_int64), ("lds_bytes_16", ctypes.c_int64),
                 ("lanes_fp32", ctypes.c_int32), ("lanes_fp16", ctypes.c_int32),
                 ("lanes_bf16", ctypes.c_int32)]
+
+
+class ldpc_problem(ctypes.Structure):
+    _fields_ = [("code", ctypes.c_void_p), ("llr", ctypes.c_void_p), ("num_frames", ctypes.c_int32),
+                ("max_iter", ctypes.c_int32), ("hard", ctypes.c_void_p), ("post", ctypes.c_void_p),
+                ("iters", ctypes.c_void_p), ("syn_ok", ctypes.c_void_p)]
+
+
+class ldpc_batch_options(ctypes.Structure):
+    _fields_ = [("lanes_per_cn", ctypes.c_int32), ("split_by_size", ctypes.c_int32),
+                ("max_threads", ctypes.c_int32), ("streams", ctypes.c_int32)]
+
+
+class ldpc_batch_info(ctypes.Structure):
+    _fields_ = [("num_launches", ctypes.c_int32), ("num_problems", ctypes.c_int32),
+                ("num_streams", ctypes.c_int32), ("total_frames", ctypes.c_int64)]
 
 
 class LdpcError(RuntimeError):
@@ -82,6 +99,17 @@ def load() -> ctypes.CDLL:
     lib.ldpc_decode.restype = ctypes.c_int
     lib.ldpc_decode.argtypes = [vp, vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_uint32,
                                 vp, vp, vp, vp, vp]
+    lib.ldpc_batch_create.restype = ctypes.c_int
+    lib.ldpc_batch_create.argtypes = [ctypes.POINTER(ldpc_problem), ctypes.c_int32, ctypes.c_uint32,
+                                      ctypes.POINTER(ldpc_batch_options), ctypes.POINTER(vp)]
+    lib.ldpc_batch_launch.restype = ctypes.c_int
+    lib.ldpc_batch_launch.argtypes = [vp, vp]
+    lib.ldpc_batch_query.restype = ctypes.c_int
+    lib.ldpc_batch_query.argtypes = [vp, ctypes.POINTER(ldpc_batch_info)]
+    lib.ldpc_batch_destroy.restype = ctypes.c_int
+    lib.ldpc_batch_destroy.argtypes = [vp]
+    lib.ldpc_decode_batched.restype = ctypes.c_int
+    lib.ldpc_decode_batched.argtypes = [ctypes.POINTER(ldpc_problem), ctypes.c_int32, ctypes.c_uint32, vp]
     lib.ldpc_last_error.restype = ctypes.c_char_p
     lib.ldpc_last_error.argtypes = []
     _lib = lib

@@ -178,6 +178,134 @@ MsgKind msg_kind(uint32_t flags) {
     return (flags & LDPC_FLAG_MSG_FP16) ? kMsgF16 : (flags & LDPC_FLAG_MSG_BF16) ? kMsgBF16 : kMsgF32;
 }
 
+int check_flags(uint32_t flags) {
+    const uint32_t known = LDPC_FLAG_EARLY_STOP | LDPC_FLAG_MSG_FP16 | LDPC_FLAG_MSG_BF16;
+    if (flags & ~known) return fail(LDPC_EINVAL, "unknown flag bits");
+    if ((flags & LDPC_FLAG_MSG_FP16) && (flags & LDPC_FLAG_MSG_BF16))
+        return fail(LDPC_EINVAL, "MSG_FP16 and MSG_BF16 are exclusive");
+    return LDPC_OK;
+}
+
+int check_lds(const ldpc_code* c, const Layout& lay, MsgKind kind) {
+    if (lds_bytes(c, lay, kind) > c->max_lds)
+        return fail(LDPC_EUNSUPPORTED, "one frame needs " + std::to_string(lds_bytes(c, lay, kind)) +
+                                           " B of LDS, device allows " + std::to_string(c->max_lds));
+    return LDPC_OK;
+}
+
+// Persistent workgroups of a launch: as many as can be resident, at most one
+// per frame.
+int set_blocks(MsgKind kind, int D, bool uniform, bool table, int num_cus, int64_t frames, LaunchShape& shape) {
+    int per_cu = 0;
+    hipError_t oe = decode_occupancy(kind, D, uniform, shape.lanes, table, shape.threads, shape.lds_bytes, &per_cu);
+    if (oe != hipSuccess) return hip_fail(oe, "occupancy query");
+    if (per_cu < 1) return fail(LDPC_EUNSUPPORTED, "kernel variant cannot be resident");
+    shape.blocks = (int)std::min<int64_t>((int64_t)per_cu * num_cus, frames);
+    return LDPC_OK;
+}
+
+Problem make_problem(const ldpc_code* c, const Layout& lay, const float* llr, int32_t num_frames, int32_t max_iter,
+                     uint8_t* hard, float* post, int32_t* iters, uint8_t* syn_ok) {
+    Problem p{};
+    p.vcn = c->dev.vcn;
+    p.vw = lay.vw;
+    p.visit_ptr = c->dev.visit_ptr;
+    p.fix = c->dev.fix;
+    p.fix_ptr = c->dev.fix_ptr;
+    p.syn_col = lay.syn_col;
+    p.llr = llr;
+    p.hard = hard;
+    p.post = post;
+    p.iters = iters;
+    p.syn_ok = syn_ok;
+    p.n = c->n;
+    p.m = c->m;
+    p.G = c->G;
+    p.max_iter = max_iter;
+    p.first = 0;
+    p.num_frames = num_frames;
+    p.ds_start_b = 4u * (uint32_t)c->ds_start;
+    p.pad_b = 4u * (uint32_t)c->n;
+    p.l_offset = (int32_t)float_bytes(c);
+    return p;
+}
+
+void set_launch_constants(DecodeArgs& a, uint32_t flags, size_t lds) {
+    a.early_stop = (flags & LDPC_FLAG_EARLY_STOP) ? 1 : 0;
+    a.sh_offset = (int32_t)(lds - 16);
+    a.ymin = (float)(kXMin * kLog2e);
+    a.ymax = (float)(kXMax * kLog2e);
+    a.cmin = (float)kXMin;
+}
+
+// Launch class of a batched problem: kernel variant, and with size
+// splitting the power of two at or above its LDS need.
+struct ClassKey {
+    int D = 0, H = 1;
+    bool uniform = false;
+    int size_class = 0;
+    bool operator<(const ClassKey& o) const {
+        if (D != o.D) return D < o.D;
+        if (H != o.H) return H < o.H;
+        if (uniform != o.uniform) return uniform < o.uniform;
+        return size_class < o.size_class;
+    }
+};
+
+int size_class(size_t lds) {
+    int k = 0;
+    while (((size_t)1 << k) < lds) ++k;
+    return k;
+}
+
+struct BatchClass {
+    ClassKey key;
+    int32_t table_offset = 0;
+    int32_t nprob = 0;
+    int32_t total_frames = 0;
+    double work_estimate = 0.0;
+    LaunchShape shape{};
+    DecodeArgs args{};
+};
+
+constexpr int kMaxBatchStreams = 8;
+
+ldpc_batch_options default_batch_options() {
+    ldpc_batch_options o;
+    o.lanes_per_cn = 0;
+    o.split_by_size = 1;
+    o.max_threads = 0;
+    o.streams = 4;
+    return o;
+}
+
+}  // namespace
+
+struct ldpc_batch {
+    int32_t device = -1;
+    MsgKind kind = kMsgF32;
+    int32_t num_problems = 0;
+    int64_t total_frames = 0;
+    std::vector<BatchClass> classes;
+    Problem* table = nullptr;  // device: every class's problems
+    uint32_t* work = nullptr;  // device: a counter pair per class
+    std::vector<hipStream_t> streams;  // streams besides the caller's
+    std::vector<hipEvent_t> events;    // fork, then one join per extra stream
+};
+
+namespace {
+
+void free_batch(ldpc_batch* b) {
+    for (hipEvent_t ev : b->events) (void)hipEventDestroy(ev);
+    for (hipStream_t st : b->streams) (void)hipStreamDestroy(st);
+    b->events.clear();
+    b->streams.clear();
+    (void)hipFree(b->table);
+    (void)hipFree(b->work);
+    b->table = nullptr;
+    b->work = nullptr;
+}
+
 }  // namespace
 
 extern "C" {
@@ -421,10 +549,8 @@ int ldpc_decode(ldpc_code_t c, const float* llr, int32_t num_frames, int32_t max
     if (!c) return fail(LDPC_EINVAL, "code is NULL");
     if (num_frames < 0) return fail(LDPC_EINVAL, "num_frames < 0");
     if (max_iter < 1) return fail(LDPC_EINVAL, "max_iter < 1");
-    const uint32_t known = LDPC_FLAG_EARLY_STOP | LDPC_FLAG_MSG_FP16 | LDPC_FLAG_MSG_BF16;
-    if (flags & ~known) return fail(LDPC_EINVAL, "unknown flag bits");
-    if ((flags & LDPC_FLAG_MSG_FP16) && (flags & LDPC_FLAG_MSG_BF16))
-        return fail(LDPC_EINVAL, "MSG_FP16 and MSG_BF16 are exclusive");
+    int rc = check_flags(flags);
+    if (rc) return rc;
     if (num_frames == 0) return LDPC_OK;
     if (!llr || !hard || !iters) return fail(LDPC_EINVAL, "llr, hard and iters are required");
     const MsgKind kind = msg_kind(flags);
@@ -432,48 +558,251 @@ int ldpc_decode(ldpc_code_t c, const float* llr, int32_t num_frames, int32_t max
 
     DeviceGuard guard(c->device);
     if (!guard.ok) return fail(LDPC_EHIP, "cannot select the code's device");
-    if (lds_bytes(c, lay, kind) > c->max_lds)
-        return fail(LDPC_EUNSUPPORTED, "one frame needs " + std::to_string(lds_bytes(c, lay, kind)) +
-                                           " B of LDS, device allows " + std::to_string(c->max_lds));
+    rc = check_lds(c, lay, kind);
+    if (rc) return rc;
     LaunchShape shape;
     shape.lanes = lay.H;
     shape.threads = threads_for(c, lay);
     shape.lds_bytes = lds_bytes(c, lay, kind);
-    int per_cu = 0;
-    hipError_t oe = decode_occupancy(kind, lay.D, lay.uniform, shape.lanes, shape.threads, shape.lds_bytes, &per_cu);
-    if (oe != hipSuccess) return hip_fail(oe, "occupancy query");
-    if (per_cu < 1) return fail(LDPC_EUNSUPPORTED, "kernel variant cannot be resident");
-    shape.blocks = (int)std::min<int64_t>((int64_t)per_cu * c->num_cus, num_frames);
+    rc = set_blocks(kind, lay.D, lay.uniform, false, c->num_cus, num_frames, shape);
+    if (rc) return rc;
 
-    DecodeArgs a;
-    a.vcn = c->dev.vcn;
-    a.vw = lay.vw;
-    a.visit_ptr = c->dev.visit_ptr;
-    a.fix = c->dev.fix;
-    a.fix_ptr = c->dev.fix_ptr;
-    a.syn_col = lay.syn_col;
-    a.llr = llr;
-    a.hard = hard;
-    a.post = post;
-    a.iters = iters;
-    a.syn_ok = syn_ok;
+    DecodeArgs a{};
+    a.p0 = make_problem(c, lay, llr, num_frames, max_iter, hard, post, iters, syn_ok);
+    a.table = nullptr;
+    a.nprob = 1;
+    a.total_frames = num_frames;
     a.work = c->dev.work + 2 * (c->next_work.fetch_add(1) % kWorkRing);
-    a.n = c->n;
-    a.m = c->m;
-    a.G = c->G;
-    a.max_iter = max_iter;
-    a.early_stop = (flags & LDPC_FLAG_EARLY_STOP) ? 1 : 0;
-    a.num_frames = num_frames;
-    a.ds_start_b = 4u * (uint32_t)c->ds_start;
-    a.pad_b = 4u * (uint32_t)c->n;
-    a.l_offset = (int32_t)float_bytes(c);
-    a.sh_offset = (int32_t)(float_bytes(c) + msg_bytes(c, lay, kind));
-    a.ymin = (float)(kXMin * kLog2e);
-    a.ymax = (float)(kXMax * kLog2e);
-    a.cmin = (float)kXMin;
+    set_launch_constants(a, flags, shape.lds_bytes);
     hipError_t e = launch_decode(a, kind, lay.D, lay.uniform, shape, (hipStream_t)hip_stream);
     if (e != hipSuccess) return hip_fail(e, "decode launch");
     return LDPC_OK;
+}
+
+int ldpc_batch_create(const ldpc_problem* probs, int32_t count, uint32_t flags, const ldpc_batch_options* opt,
+                      ldpc_batch_t* out) {
+    g_last_error.clear();
+    if (!out) return fail(LDPC_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (count < 0) return fail(LDPC_EINVAL, "count < 0");
+    if (count > 0 && !probs) return fail(LDPC_EINVAL, "probs is NULL");
+    int rc = check_flags(flags);
+    if (rc) return rc;
+    ldpc_batch_options o = default_batch_options();
+    if (opt) o = *opt;
+    if (o.lanes_per_cn < 0 || o.lanes_per_cn > 2) return fail(LDPC_EINVAL, "lanes_per_cn must be 0, 1 or 2");
+    if (o.max_threads < 0 || o.max_threads % 64 || o.max_threads > 1024)
+        return fail(LDPC_EINVAL, "max_threads must be 0 or a multiple of 64 up to 1024");
+    if (o.streams < 0 || o.streams > kMaxBatchStreams) return fail(LDPC_EINVAL, "streams must be in 0..8");
+    const MsgKind kind = msg_kind(flags);
+
+    // validate; pick each problem's mapping and class
+    struct Item {
+        int idx;
+        const Layout* lay;
+        ClassKey key;
+        size_t lds;
+        int threads;
+    };
+    std::vector<Item> items;
+    int32_t device = -1;
+    int num_cus = 0;
+    size_t max_lds = 0;
+    for (int i = 0; i < count; ++i) {
+        const ldpc_problem& q = probs[i];
+        const std::string at = "problem " + std::to_string(i) + ": ";
+        if (!q.code) return fail(LDPC_EINVAL, at + "code is NULL");
+        if (q.num_frames < 0) return fail(LDPC_EINVAL, at + "num_frames < 0");
+        if (q.max_iter < 1) return fail(LDPC_EINVAL, at + "max_iter < 1");
+        if (device < 0) {
+            device = q.code->device;
+            num_cus = q.code->num_cus;
+            max_lds = q.code->max_lds;
+        } else if (q.code->device != device) {
+            return fail(LDPC_EINVAL, at + "codes of one batch must be on one device");
+        }
+        if (q.num_frames == 0) continue;
+        if (!q.llr || !q.hard || !q.iters) return fail(LDPC_EINVAL, at + "llr, hard and iters are required");
+        const int h = o.lanes_per_cn ? o.lanes_per_cn : q.code->lanes_for[kind];
+        const Layout& lay = q.code->lay[h - 1];
+        if (!lay.valid) return fail(LDPC_EUNSUPPORTED, at + "no kernel variant with that mapping");
+        rc = check_lds(q.code, lay, kind);
+        if (rc) return fail(rc, at + g_last_error);
+        Item it;
+        it.idx = i;
+        it.lay = &lay;
+        it.lds = lds_bytes(q.code, lay, kind);
+        it.threads = threads_for(q.code, lay);
+        it.key.D = lay.D;
+        it.key.H = lay.H;
+        it.key.uniform = lay.uniform;
+        it.key.size_class = o.split_by_size ? size_class(it.lds) : 0;
+        items.push_back(it);
+    }
+
+    ldpc_batch* b = new (std::nothrow) ldpc_batch();
+    if (!b) return fail(LDPC_ENOMEM, "host allocation failed");
+    b->device = device;
+    b->kind = kind;
+    b->num_problems = count;
+
+    // classes: one persistent launch each
+    std::stable_sort(items.begin(), items.end(), [](const Item& x, const Item& y) { return x.key < y.key; });
+    std::vector<Problem> table;
+    for (size_t s = 0; s < items.size();) {
+        size_t e = s;
+        while (e < items.size() && !(items[s].key < items[e].key) && !(items[e].key < items[s].key)) ++e;
+        BatchClass bc;
+        bc.key = items[s].key;
+        bc.table_offset = (int32_t)table.size();
+        size_t lds = 0;
+        int threads = 64;
+        int64_t frames = 0;
+        double work = 0.0;
+        for (size_t k = s; k < e; ++k) {
+            const ldpc_problem& q = probs[items[k].idx];
+            if (frames + q.num_frames > INT32_MAX) {
+                delete b;
+                return fail(LDPC_EUNSUPPORTED, "more than 2^31 - 1 frames in one launch class");
+            }
+            table.push_back(make_problem(q.code, *items[k].lay, q.llr, q.num_frames, q.max_iter, q.hard, q.post,
+                                         q.iters, q.syn_ok));
+            table.back().first = (int32_t)frames;
+            frames += q.num_frames;
+            work += (double)q.num_frames * (double)q.code->edge_updates * q.max_iter;
+            lds = std::max(lds, items[k].lds);
+            threads = std::max(threads, items[k].threads);
+        }
+        if (o.max_threads) threads = std::min(threads, o.max_threads);
+        bc.nprob = (int32_t)(e - s);
+        bc.total_frames = (int32_t)frames;
+        bc.work_estimate = work;
+        bc.shape.lanes = bc.key.H;
+        bc.shape.threads = threads;
+        bc.shape.lds_bytes = lds;
+        b->total_frames += frames;
+        b->classes.push_back(bc);
+        s = e;
+    }
+    // the longest launches first, so that short ones fill the tails
+    std::stable_sort(b->classes.begin(), b->classes.end(),
+                     [](const BatchClass& x, const BatchClass& y) { return x.work_estimate > y.work_estimate; });
+
+    if (b->classes.empty()) {
+        *out = b;
+        return LDPC_OK;
+    }
+    DeviceGuard guard(device);
+    if (!guard.ok) {
+        delete b;
+        return fail(LDPC_EHIP, "cannot select the batch's device");
+    }
+    (void)max_lds;
+    for (BatchClass& bc : b->classes) {
+        rc = set_blocks(kind, bc.key.D, bc.key.uniform, true, num_cus, bc.total_frames, bc.shape);
+        if (rc) {
+            delete b;
+            return rc;
+        }
+    }
+    hipError_t e = upload(&b->table, table);
+    if (e == hipSuccess) e = hipMalloc((void**)&b->work, 2 * sizeof(uint32_t) * b->classes.size());
+    if (e == hipSuccess) e = hipMemset(b->work, 0, 2 * sizeof(uint32_t) * b->classes.size());
+    const int nstreams = std::min<int>(std::max(1, o.streams), (int)b->classes.size());
+    for (int k = 1; k < nstreams && e == hipSuccess; ++k) {
+        hipStream_t st = nullptr;
+        e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
+        if (e == hipSuccess) b->streams.push_back(st);
+    }
+    for (int k = 0; k < nstreams && e == hipSuccess; ++k) {
+        hipEvent_t ev = nullptr;
+        e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+        if (e == hipSuccess) b->events.push_back(ev);
+    }
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e != hipSuccess) {
+        free_batch(b);
+        delete b;
+        return hip_fail(e, "batch tables");
+    }
+    for (size_t k = 0; k < b->classes.size(); ++k) {
+        BatchClass& bc = b->classes[k];
+        DecodeArgs& a = bc.args;
+        a = DecodeArgs{};
+        a.p0 = table[bc.table_offset];
+        a.table = b->table + bc.table_offset;
+        a.nprob = bc.nprob;
+        a.total_frames = bc.total_frames;
+        a.work = b->work + 2 * k;
+        set_launch_constants(a, flags, bc.shape.lds_bytes);
+    }
+    *out = b;
+    return LDPC_OK;
+}
+
+int ldpc_batch_query(ldpc_batch_t b, ldpc_batch_info* info) {
+    g_last_error.clear();
+    if (!b || !info) return fail(LDPC_EINVAL, "batch or info is NULL");
+    info->num_launches = (int32_t)b->classes.size();
+    info->num_problems = b->num_problems;
+    info->num_streams = (int32_t)b->streams.size() + 1;
+    info->total_frames = b->total_frames;
+    return LDPC_OK;
+}
+
+int ldpc_batch_launch(ldpc_batch_t b, void* hip_stream) {
+    g_last_error.clear();
+    if (!b) return fail(LDPC_EINVAL, "batch is NULL");
+    if (b->classes.empty()) return LDPC_OK;
+    DeviceGuard guard(b->device);
+    if (!guard.ok) return fail(LDPC_EHIP, "cannot select the batch's device");
+    hipStream_t main = (hipStream_t)hip_stream;
+    const int ns = (int)b->streams.size() + 1;
+    hipError_t e = hipSuccess;
+    if (ns > 1) {
+        // fork: the other streams start after the work already on `main`
+        e = hipEventRecord(b->events[0], main);
+        for (int k = 1; k < ns && e == hipSuccess; ++k) e = hipStreamWaitEvent(b->streams[k - 1], b->events[0], 0);
+    }
+    for (size_t k = 0; k < b->classes.size() && e == hipSuccess; ++k) {
+        const BatchClass& bc = b->classes[k];
+        hipStream_t st = k % ns == 0 ? main : b->streams[k % ns - 1];
+        e = launch_decode(bc.args, b->kind, bc.key.D, bc.key.uniform, bc.shape, st);
+    }
+    // join: `main` continues after every launch
+    for (int k = 1; k < ns && e == hipSuccess; ++k) {
+        e = hipEventRecord(b->events[k], b->streams[k - 1]);
+        if (e == hipSuccess) e = hipStreamWaitEvent(main, b->events[k], 0);
+    }
+    if (e != hipSuccess) return hip_fail(e, "batch launch");
+    return LDPC_OK;
+}
+
+int ldpc_batch_destroy(ldpc_batch_t b) {
+    g_last_error.clear();
+    if (!b) return LDPC_OK;
+    if (b->table || b->work || !b->streams.empty() || !b->events.empty()) {
+        DeviceGuard guard(b->device);
+        free_batch(b);
+    }
+    delete b;
+    return LDPC_OK;
+}
+
+int ldpc_decode_batched(const ldpc_problem* probs, int32_t count, uint32_t flags, void* hip_stream) {
+    ldpc_batch_t b = nullptr;
+    int rc = ldpc_batch_create(probs, count, flags, nullptr, &b);
+    if (rc) return rc;
+    rc = ldpc_batch_launch(b, hip_stream);
+    if (rc == LDPC_OK && !b->classes.empty()) {
+        DeviceGuard guard(b->device);
+        hipError_t e = hipStreamSynchronize((hipStream_t)hip_stream);
+        if (e != hipSuccess) rc = hip_fail(e, "batched decode");
+    }
+    std::string msg = g_last_error;
+    ldpc_batch_destroy(b);
+    g_last_error = msg;
+    return rc;
 }
 
 }  // extern "C"

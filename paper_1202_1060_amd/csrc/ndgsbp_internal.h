@@ -52,7 +52,8 @@ constexpr double kXMin = 1.8715245937680347e-13;
 //     then delta slots;
 //   at l_offset: message rows, row (cn * H + h) of lane h of CN cn holding
 //     DH messages (FP32, or 16-bit with DH rounded up to even);
-//   at sh_offset: int frame, int flag[2].
+//   at sh_offset (the last 16 bytes of the allocation, the same for every
+//     problem of a launch): int frame, int flag[2], int problem.
 
 struct DeviceTables {
     int32_t* vcn = nullptr;
@@ -72,7 +73,9 @@ struct Layout {
     uint32_t* syn_col = nullptr;  // m * SD
 };
 
-struct DecodeArgs {
+// One decode problem: a code's tables for one CN-lane mapping and the
+// buffers of one call.
+struct Problem {
     const int32_t* vcn;
     const uint32_t* vw;
     const int32_t* visit_ptr;
@@ -84,17 +87,29 @@ struct DecodeArgs {
     float* post;
     int32_t* iters;
     uint8_t* syn_ok;
-    uint32_t* work;     // this launch's {next frame, finished workgroups}, zero at launch
     int32_t n, m, G;
     int32_t max_iter;
-    int32_t early_stop;
+    int32_t first;        // launch-wide index of the problem's first frame
     int32_t num_frames;
     uint32_t ds_start_b;  // byte offset of the first delta slot
-    uint32_t pad_b;     // byte offset of the scratch posterior n of padding edges
-    int32_t l_offset;   // byte offset of the message rows
-    int32_t sh_offset;  // byte offset of the frame index and flags
-    float ymin, ymax;   // clamp of |VN->CN message|, log2 units
-    float cmin;         // lower clamp of the complement 1 - prod tanh
+    uint32_t pad_b;       // byte offset of the scratch posterior n of padding edges
+    int32_t l_offset;     // byte offset of the message rows
+    int32_t reserved;
+};
+
+// Kernel arguments. A launch decodes p0 (table == nullptr) or the nprob
+// problems of a device table sorted by `first`, whose frames it numbers
+// 0 .. total_frames - 1 in table order.
+struct DecodeArgs {
+    Problem p0;
+    const Problem* table;
+    int32_t nprob;
+    int32_t total_frames;
+    uint32_t* work;       // this launch's {next frame, finished workgroups}, zero at launch
+    int32_t early_stop;
+    int32_t sh_offset;    // byte offset of the workgroup state (frame, flags, problem)
+    float ymin, ymax;     // clamp of |VN->CN message|, log2 units
+    float cmin;           // lower clamp of the complement 1 - prod tanh
 };
 
 struct LaunchShape {
@@ -110,8 +125,9 @@ enum MsgKind { kMsgF32 = 0, kMsgF16 = 1, kMsgBF16 = 2 };
 hipError_t launch_decode(const DecodeArgs& a, MsgKind kind, int dmax, bool uniform, const LaunchShape& shape,
                          hipStream_t stream);
 // Resident workgroups per CU of a kernel variant.
-hipError_t decode_occupancy(MsgKind kind, int dmax, bool uniform, int lanes, int threads, size_t lds_bytes,
-                            int* blocks_per_cu);
+// `table`: the batched kernel (problems read from a device table).
+hipError_t decode_occupancy(MsgKind kind, int dmax, bool uniform, int lanes, bool table, int threads,
+                            size_t lds_bytes, int* blocks_per_cu);
 int max_threads_for_degree(int dmax);
 // Bytes of the message rows of one CN.
 int message_row_bytes(MsgKind kind, int dmax, int lanes);

@@ -105,10 +105,10 @@ struct VisitRegs {
 // Visit records of a group start at the uniform address of visit j0; this
 // lane's record is `item` visits further, half h.
 template <int DH, int H>
-__device__ __forceinline__ void load_visit(const DecodeArgs& a, int j0, int item, int h, VisitRegs<DH>& r) {
+__device__ __forceinline__ void load_visit(const Problem& p, int j0, int item, int h, VisitRegs<DH>& r) {
     constexpr int W = VisitRegs<DH>::kWords;
-    const unsigned char* cbase = reinterpret_cast<const unsigned char*>(a.vcn) + (size_t)j0 * 4;
-    const unsigned char* wbase = reinterpret_cast<const unsigned char*>(a.vw) + (size_t)j0 * (H * W * 4);
+    const unsigned char* cbase = reinterpret_cast<const unsigned char*>(p.vcn) + (size_t)j0 * 4;
+    const unsigned char* wbase = reinterpret_cast<const unsigned char*>(p.vw) + (size_t)j0 * (H * W * 4);
     r.cn = *reinterpret_cast<const int32_t*>(cbase + (uint32_t)item * 4u);
     const uint4* src = reinterpret_cast<const uint4*>(wbase + (uint32_t)(item * H + h) * (uint32_t)(W * 4));
     uint32_t w[W];
@@ -139,10 +139,11 @@ __device__ __forceinline__ uint32_t pair_swap(uint32_t x) {
 // their partial combinations and sign parities by DPP.
 // UNI: every CN has degree D, so no edge is padding.
 template <class M, int D, bool UNI, int H>
-__device__ __forceinline__ void cn_visit(const DecodeArgs& a, const VisitRegs<D / H>& r, uint32_t h) {
+__device__ __forceinline__ void cn_visit(const DecodeArgs& a, const Problem& p, const VisitRegs<D / H>& r,
+                                         uint32_t h) {
     constexpr int DH = D / H;
     using R = Row<M, DH>;
-    const uint32_t row = (uint32_t)a.l_offset + __umul24((uint32_t)(r.cn * H) + h, (uint32_t)R::kBytes);
+    const uint32_t row = (uint32_t)p.l_offset + __umul24((uint32_t)(r.cn * H) + h, (uint32_t)R::kBytes);
     float t[DH], lo[DH], e[DH];
     uint32_t tb[DH];
     uint32_t sall = 0;
@@ -154,7 +155,7 @@ __device__ __forceinline__ void cn_visit(const DecodeArgs& a, const VisitRegs<D 
         tb[k] = __float_as_uint(t[k]);
         e[k] = tanh_complement(exp2_hw(-clampf(fabsf(t[k]), a.ymin, a.ymax)));
         if (!UNI) {
-            const bool real = r.pa[k] != a.pad_b;
+            const bool real = r.pa[k] != p.pad_b;
             e[k] = real ? e[k] : 0.0f;  // 0 is the identity of (+)
             tb[k] = real ? tb[k] : 0u;
         }
@@ -189,7 +190,7 @@ __device__ __forceinline__ void cn_visit(const DecodeArgs& a, const VisitRegs<D 
         const float ls = M::unpack(st[k]);
         // posterior add-back (the VN's only edge in this group), or the
         // delta new - old for the fix-up pass
-        const bool direct = r.ta[k] < a.ds_start_b;
+        const bool direct = r.ta[k] < p.ds_start_b;
         lds_f32(r.ta[k]) = ls + (direct ? t[k] : -lo[k]);
     }
     R::store(row, st);
@@ -201,38 +202,78 @@ struct MaxThreads {
     static constexpr int value = D >= 24 ? 256 : 1024;
 };
 
-// Takes the next frame index from the launch's work counter (-1: none left).
-__device__ __forceinline__ int claim_frame(const DecodeArgs& a) {
+// Takes the next frame of the launch from its work counter (thread 0) and
+// stores, at the workgroup state, the frame's index within its problem (-1:
+// none left) and the problem's index.
+__device__ __forceinline__ void claim_frame(const DecodeArgs& a, uint32_t sh) {
     const unsigned t = atomicAdd(a.work, 1u);
-    return t < (unsigned)a.num_frames ? (int)t : -1;
+    int frame = -1, prob = 0;
+    if (t < (unsigned)a.total_frames) {
+        frame = (int)t;
+        if (a.table) {
+            // last problem whose first frame is at or before t
+            int lo = 0, hi = a.nprob - 1;
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (a.table[mid].first <= (int)t)
+                    lo = mid;
+                else
+                    hi = mid - 1;
+            }
+            prob = lo;
+            frame = (int)t - a.table[lo].first;
+        }
+    }
+    lds_i32(sh) = frame;
+    lds_i32(sh + 12) = prob;
+}
+
+// Problem `idx` of the launch; the table is read through the constant
+// address space so that the fields land in scalar registers.
+static_assert(sizeof(Problem) % 16 == 0, "Problem is read as 16-byte words");
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+struct ProblemWords {
+    u32x4 w[sizeof(Problem) / 16];
+};
+template <bool TABLE>
+__device__ __forceinline__ Problem get_problem(const DecodeArgs& a, int idx) {
+    typedef const __attribute__((address_space(4))) u32x4 const_u4;
+    if constexpr (!TABLE) return a.p0;
+    const const_u4* src = (const const_u4*)(a.table + idx);
+    ProblemWords pw;
+#pragma unroll
+    for (int i = 0; i < (int)(sizeof(Problem) / 16); ++i) pw.w[i] = src[i];
+    return __builtin_bit_cast(Problem, pw);
 }
 
 template <class M, int D, int H>
-__device__ __forceinline__ void init_frame(const DecodeArgs& a, int frame, int tid, int nt) {
-    const float* y = a.llr + (size_t)frame * a.n;
-    for (int v = tid; v < a.n; v += nt) lds_f32(4u * v) = y[v] * kLog2eF + 0.0f;  // + 0 turns -0.0 into +0.0
+__device__ __forceinline__ void init_frame(const Problem& p, int frame, int tid, int nt) {
+    const float* y = p.llr + (size_t)frame * p.n;
+    for (int v = tid; v < p.n; v += nt) lds_f32(4u * v) = y[v] * kLog2eF + 0.0f;  // + 0 turns -0.0 into +0.0
     // posterior n: scratch of padding edges; n + 1: 0, padding of syndrome rows
-    if (tid < 2) lds_f32(4u * (a.n + tid)) = 0.0f;
+    if (tid < 2) lds_f32(4u * (p.n + tid)) = 0.0f;
     // messages start at 0 (every format stores +0 as all-zero bits)
-    const int words = a.m * H * Row<M, D / H>::kWords;
-    for (int q = tid; q < words; q += nt) lds_i32((uint32_t)a.l_offset + 4u * q) = 0;
+    const int words = p.m * H * Row<M, D / H>::kWords;
+    for (int q = tid; q < words; q += nt) lds_i32((uint32_t)p.l_offset + 4u * q) = 0;
 }
 
-__device__ __forceinline__ void write_outputs(const DecodeArgs& a, int frame, int used, int fail, int tid, int nt) {
-    uint8_t* hd = a.hard + (size_t)frame * a.n;
-    float* po = a.post ? a.post + (size_t)frame * a.n : nullptr;
-    for (int v = tid; v < a.n; v += nt) {
+__device__ __forceinline__ void write_outputs(const Problem& p, int frame, int used, int fail, int tid, int nt) {
+    uint8_t* hd = p.hard + (size_t)frame * p.n;
+    float* po = p.post ? p.post + (size_t)frame * p.n : nullptr;
+    for (int v = tid; v < p.n; v += nt) {
         const float x = lds_f32(4u * v);
         hd[v] = x < 0.0f ? 1 : 0;
         if (po) po[v] = x * kLn2F;
     }
     if (tid == 0) {
-        a.iters[frame] = used;
-        if (a.syn_ok) a.syn_ok[frame] = fail ? 0 : 1;
+        p.iters[frame] = used;
+        if (p.syn_ok) p.syn_ok[frame] = fail ? 0 : 1;
     }
 }
 
-template <class M, int D, bool UNI, int H>
+// TABLE: the launch reads its problems from a.table (batched decoding);
+// otherwise it decodes a.p0, whose fields stay kernel arguments.
+template <class M, int D, bool UNI, int H, bool TABLE>
 __global__ __launch_bounds__(MaxThreads<D>::value) void ndgsbp_kernel(DecodeArgs a) {
     constexpr int DH = D / H;
     constexpr int SD = (D + 3) / 4 * 4;  // syndrome row stride (entries)
@@ -240,52 +281,54 @@ __global__ __launch_bounds__(MaxThreads<D>::value) void ndgsbp_kernel(DecodeArgs
     const int tid = threadIdx.x, nt = blockDim.x;
     // CN phase: this lane is half lh of visit vitem
     const int lh = tid % H, vitem = tid / H, nvitem = nt / H;
-    // state in LDS: the frame index, and "some check failed" flags
-    // alternating by iteration parity
+    // state in LDS: the frame index, "some check failed" flags alternating
+    // by iteration parity, and the problem index
     const uint32_t sh = (uint32_t)a.sh_offset;
     if ((size_t)(__attribute__((address_space(3))) unsigned char*)smem != 0) {
         // dynamic LDS does not start at 0: the byte offsets would be wrong
-        if (tid == 0 && a.num_frames > 0) a.iters[0] = -1;
+        if (tid == 0 && a.total_frames > 0) get_problem<TABLE>(a, 0).iters[0] = -1;
         return;
     }
 
     if (tid == 0) {
-        lds_i32(sh) = claim_frame(a);
+        claim_frame(a, sh);
         lds_i32(sh + 4) = 0;
         lds_i32(sh + 8) = 0;
     }
     __syncthreads();
-    int frame = lds_i32(sh);
+    int frame = __builtin_amdgcn_readfirstlane(lds_i32(sh));
+    int pid = TABLE ? __builtin_amdgcn_readfirstlane(lds_i32(sh + 12)) : 0;
+    Problem p = get_problem<TABLE>(a, pid);
     int used = 0;
-    if (frame >= 0) init_frame<M, D, H>(a, frame, tid, nt);
+    if (frame >= 0) init_frame<M, D, H>(p, frame, tid, nt);
     // the first visit of every lane is fetched one group ahead
     VisitRegs<DH> nxt;
-    bool have_nxt = vitem < table_i32(a.visit_ptr, 1);
-    if (have_nxt) load_visit<DH, H>(a, 0, vitem, lh, nxt);
+    bool have_nxt = vitem < table_i32(p.visit_ptr, 1);
+    if (have_nxt) load_visit<DH, H>(p, 0, vitem, lh, nxt);
     __syncthreads();
 
     for (int step = 0; frame >= 0; ++step) {
-        for (int g = 0; g < a.G; ++g) {
+        for (int g = 0; g < p.G; ++g) {
             const VisitRegs<DH> cur = nxt;
             const bool have_cur = have_nxt;
-            const int gn = g + 1 == a.G ? 0 : g + 1;
-            const int jn0 = table_i32(a.visit_ptr, gn), jn1 = table_i32(a.visit_ptr, gn + 1);
+            const int gn = g + 1 == p.G ? 0 : g + 1;
+            const int jn0 = table_i32(p.visit_ptr, gn), jn1 = table_i32(p.visit_ptr, gn + 1);
             have_nxt = vitem < jn1 - jn0;
-            if (have_nxt) load_visit<DH, H>(a, jn0, vitem, lh, nxt);
-            if (have_cur) cn_visit<M, D, UNI, H>(a, cur, lh);
-            const int j0 = table_i32(a.visit_ptr, g), j1 = table_i32(a.visit_ptr, g + 1);
+            if (have_nxt) load_visit<DH, H>(p, jn0, vitem, lh, nxt);
+            if (have_cur) cn_visit<M, D, UNI, H>(a, p, cur, lh);
+            const int j0 = table_i32(p.visit_ptr, g), j1 = table_i32(p.visit_ptr, g + 1);
             for (int item = vitem + nvitem; item < j1 - j0; item += nvitem) {
                 VisitRegs<DH> extra;
-                load_visit<DH, H>(a, j0, item, lh, extra);
-                cn_visit<M, D, UNI, H>(a, extra, lh);
+                load_visit<DH, H>(p, j0, item, lh, extra);
+                cn_visit<M, D, UNI, H>(a, p, extra, lh);
             }
             __syncthreads();
-            const int q0 = table_i32(a.fix_ptr, g), q1 = table_i32(a.fix_ptr, g + 1);
+            const int q0 = table_i32(p.fix_ptr, g), q1 = table_i32(p.fix_ptr, g + 1);
             if (q1 > q0) {
                 for (int q = q0 + tid; q < q1; q += nt) {
-                    const uint2 e = a.fix[q];
+                    const uint2 e = p.fix[q];
                     const uint32_t v = e.x & 0xffffu, c = e.x >> 16;
-                    const uint32_t d0 = a.ds_start_b + 4u * e.y;
+                    const uint32_t d0 = p.ds_start_b + 4u * e.y;
                     float acc = lds_f32(4u * v);
                     for (uint32_t k = 0; k < c; ++k) acc += lds_f32(d0 + 4u * k);
                     lds_f32(4u * v) = acc;
@@ -295,16 +338,18 @@ __global__ __launch_bounds__(MaxThreads<D>::value) void ndgsbp_kernel(DecodeArgs
         }
         // a4: hard decisions (d = 1 iff total < 0) and the syndrome over all checks
         used += 1;
-        const bool check = a.early_stop || used == a.max_iter;
-        if (!check) continue;
         const uint32_t fl = sh + 4u + 4u * (step & 1);        // this step's flag
         const uint32_t fo = sh + 4u + 4u * ((step + 1) & 1);  // last read before this step
+        // cleared every step, so the next step starts from 0 whether or not
+        // this one checks (the group barriers order it after the last read)
         if (tid == 0) lds_i32(fo) = 0;
+        const bool check = a.early_stop || used == p.max_iter;
+        if (!check) continue;
         // the sign bit of a posterior is its hard decision (no -0.0); a lane
         // stops once any check has been seen to fail
-        for (int c = tid; c < a.m; c += nt) {
+        for (int c = tid; c < p.m; c += nt) {
             if (lds_i32(fl)) break;
-            const uint4* col = reinterpret_cast<const uint4*>(a.syn_col + (size_t)c * SD);
+            const uint4* col = reinterpret_cast<const uint4*>(p.syn_col + (size_t)c * SD);
             uint32_t x = 0;
 #pragma unroll
             for (int q = 0; q < SD / 4; ++q) {
@@ -316,14 +361,26 @@ __global__ __launch_bounds__(MaxThreads<D>::value) void ndgsbp_kernel(DecodeArgs
         }
         __syncthreads();
         const int fail = lds_i32(fl);
-        if (!((a.early_stop && !fail) || used == a.max_iter)) continue;
-        // finished: outputs, then the next frame
-        write_outputs(a, frame, used, fail, tid, nt);
-        if (tid == 0) lds_i32(sh) = claim_frame(a);
+        if (!((a.early_stop && !fail) || used == p.max_iter)) continue;
+        // finished: outputs, then the next frame (of this or another problem)
+        write_outputs(p, frame, used, fail, tid, nt);
+        if (tid == 0) claim_frame(a, sh);
         __syncthreads();
-        frame = lds_i32(sh);
+        frame = __builtin_amdgcn_readfirstlane(lds_i32(sh));
         used = 0;
-        if (frame >= 0) init_frame<M, D, H>(a, frame, tid, nt);
+        if (frame >= 0) {
+            if constexpr (TABLE) {
+                const int np = __builtin_amdgcn_readfirstlane(lds_i32(sh + 12));
+                if (np != pid) {
+                    // another problem: its tables, and its first group fetched again
+                    pid = np;
+                    p = get_problem<TABLE>(a, pid);
+                    have_nxt = vitem < table_i32(p.visit_ptr, 1);
+                    if (have_nxt) load_visit<DH, H>(p, 0, vitem, lh, nxt);
+                }
+            }
+            init_frame<M, D, H>(p, frame, tid, nt);
+        }
         __syncthreads();
     }
 
@@ -341,7 +398,8 @@ __global__ __launch_bounds__(MaxThreads<D>::value) void ndgsbp_kernel(DecodeArgs
 template <class M, int D, bool UNI, int H>
 struct LaunchF {
     static hipError_t run(const DecodeArgs* a, const LaunchShape* sh, hipStream_t s) {
-        const void* fn = reinterpret_cast<const void*>(&ndgsbp_kernel<M, D, UNI, H>);
+        const void* fn = a->table ? reinterpret_cast<const void*>(&ndgsbp_kernel<M, D, UNI, H, true>)
+                                  : reinterpret_cast<const void*>(&ndgsbp_kernel<M, D, UNI, H, false>);
         hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh->lds_bytes);
         if (e != hipSuccess) return e;
         DecodeArgs copy = *a;
@@ -352,8 +410,9 @@ struct LaunchF {
 
 template <class M, int D, bool UNI, int H>
 struct OccupancyF {
-    static hipError_t run(int threads, size_t lds, int* out) {
-        const void* fn = reinterpret_cast<const void*>(&ndgsbp_kernel<M, D, UNI, H>);
+    static hipError_t run(bool table, int threads, size_t lds, int* out) {
+        const void* fn = table ? reinterpret_cast<const void*>(&ndgsbp_kernel<M, D, UNI, H, true>)
+                               : reinterpret_cast<const void*>(&ndgsbp_kernel<M, D, UNI, H, false>);
         hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
         return hipOccupancyMaxActiveBlocksPerMultiprocessor(out, fn, threads, lds);
@@ -416,9 +475,9 @@ hipError_t launch_decode(const DecodeArgs& a, MsgKind kind, int dmax, bool unifo
     return dispatch<LaunchF>(kind, dmax, uniform, shape.lanes, &a, &shape, stream);
 }
 
-hipError_t decode_occupancy(MsgKind kind, int dmax, bool uniform, int lanes, int threads, size_t lds_bytes,
-                            int* blocks_per_cu) {
-    return dispatch<OccupancyF>(kind, dmax, uniform, lanes, threads, lds_bytes, blocks_per_cu);
+hipError_t decode_occupancy(MsgKind kind, int dmax, bool uniform, int lanes, bool table, int threads,
+                            size_t lds_bytes, int* blocks_per_cu) {
+    return dispatch<OccupancyF>(kind, dmax, uniform, lanes, table, threads, lds_bytes, blocks_per_cu);
 }
 
 }  // namespace ndgsbp

@@ -76,3 +76,16 @@ def compare(gpu, ref, rtol=RTOL, atol=ATOL, k_sens=K_SENS):
     assert match.sum() >= MIN_FRAME_MATCH * F or nc_mis <= max(1, int(0.02 * nc.sum())), \
         f"decisions match on {int(match.sum())}/{F} frames"
     return stats
+
+
+def syndrome_zero(code, hard):
+    """Per frame: True iff the hard decisions satisfy every check of
+    ``code`` (computed on the host from H, independent of both decoders)."""
+    hard = np.asarray(hard, dtype=np.uint8)
+    rp = np.asarray(code.row_ptr, dtype=np.int64)
+    ci = np.asarray(code.col_idx, dtype=np.int64)
+    bits = hard[:, ci]
+    par = np.zeros((hard.shape[0], len(rp) - 1), dtype=np.uint8)
+    nz = rp[1:] > rp[:-1]
+    par[:, nz] = np.bitwise_xor.reduceat(bits, rp[:-1][nz], axis=1)
+    return ~np.any(par, axis=1)

@@ -19,7 +19,9 @@ def _declared():
 
 def test_header_declares_the_abi():
     assert _declared() == sorted(["ldpc_code_create", "ldpc_code_destroy", "ldpc_code_query",
-                                  "ldpc_code_tune", "ldpc_decode", "ldpc_last_error"])
+                                  "ldpc_code_tune", "ldpc_decode", "ldpc_batch_create",
+                                  "ldpc_batch_launch", "ldpc_batch_query", "ldpc_batch_destroy",
+                                  "ldpc_decode_batched", "ldpc_last_error"])
 
 
 def test_library_exports_every_declared_symbol():
@@ -105,6 +107,39 @@ def test_tune_rejects_null_code(nd):
     with pytest.raises(nd.LdpcError) as ei:
         nd.ldpc_code_tune(0, 0, 1)
     assert ei.value.code == nd.LDPC_EINVAL
+
+
+def test_batch_argument_errors(nd):
+    """Argument checks of the batch entry points that run before any HIP
+    call; an empty batch needs no device at all."""
+    import ctypes
+    from paper_1202_1060_amd import _native
+    lib = _native.load()
+    out = ctypes.c_void_p()
+    assert lib.ldpc_batch_create(None, 0, 0, None, None) == nd.LDPC_EINVAL
+    assert lib.ldpc_batch_create(None, -1, 0, None, ctypes.byref(out)) == nd.LDPC_EINVAL
+    assert lib.ldpc_batch_create(None, 1, 0, None, ctypes.byref(out)) == nd.LDPC_EINVAL
+    assert lib.ldpc_batch_create(None, 0, 0x100, None, ctypes.byref(out)) == nd.LDPC_EINVAL
+    assert lib.ldpc_batch_create(None, 0, nd.LDPC_FLAG_MSG_FP16 | nd.LDPC_FLAG_MSG_BF16, None,
+                                 ctypes.byref(out)) == nd.LDPC_EINVAL
+    for bad in ((3, 1, 0, 4), (0, 1, 100, 4), (0, 1, 2048, 4), (0, 1, 0, 9), (0, 1, 0, -1)):
+        opt = _native.ldpc_batch_options(*bad)
+        assert lib.ldpc_batch_create(None, 0, 0, ctypes.byref(opt), ctypes.byref(out)) == nd.LDPC_EINVAL, bad
+    probs = (_native.ldpc_problem * 1)()
+    probs[0].code = None
+    probs[0].num_frames = 4
+    probs[0].max_iter = 10
+    assert lib.ldpc_batch_create(probs, 1, 0, None, ctypes.byref(out)) == nd.LDPC_EINVAL
+    assert "code is NULL" in nd.ldpc_last_error()
+    assert lib.ldpc_batch_create(None, 0, 0, None, ctypes.byref(out)) == nd.LDPC_OK
+    info = _native.ldpc_batch_info()
+    assert lib.ldpc_batch_query(out, ctypes.byref(info)) == nd.LDPC_OK
+    assert (info.num_launches, info.num_problems, info.total_frames) == (0, 0, 0)
+    assert lib.ldpc_batch_launch(out, None) == nd.LDPC_OK
+    assert lib.ldpc_batch_destroy(out) == nd.LDPC_OK
+    assert lib.ldpc_batch_launch(None, None) == nd.LDPC_EINVAL
+    assert lib.ldpc_batch_destroy(None) == nd.LDPC_OK
+    assert lib.ldpc_decode_batched(None, 0, 0, None) == nd.LDPC_OK
 
 
 def test_destroy_null_is_ok(nd):
