@@ -81,6 +81,92 @@ def cpu_baseline(code, groups, llr, rec, frames_per_snr, sample_per_snr, k_info)
                 seconds=dt)
 
 
+def clopper_pearson(k, n, alpha=0.05):
+    from scipy.stats import beta
+    lo = 0.0 if k == 0 else float(beta.ppf(alpha / 2, k, n - k + 1))
+    hi = 1.0 if k == n else float(beta.ppf(1 - alpha / 2, k + 1, n - k))
+    return lo, hi
+
+
+def bench_batched(args, torch, nd, W, dev, log):
+    """Mixed batch of 256 QC problems: one FP16 batch plan (autotuned launch
+    options) against a plain FP32 ldpc_decode per problem, same frames."""
+    from paper_1202_1060_amd import autotune
+    rec = W.BATCH
+    specs = W.batch_problems(rec)
+    t0 = time.perf_counter()
+    codes, llrs, cws, ks = [], [], [], []
+    cache = {}
+    for p in specs:
+        llr, cw = W.problem_frames(p)
+        if p["code"] not in cache:
+            cache[p["code"]] = W.CODES[p["code"]]()
+        codes.append(nd.Code(cache[p["code"]], windows=p["windows"]))
+        llrs.append(torch.from_numpy(llr).to(dev))
+        cws.append(cw)
+        ks.append(W.encoder_for(p["code"]).k)
+    frames = np.array([p["frames"] for p in specs])
+    bits = float(np.dot(frames, ks))
+    log(f"batched inputs: {len(specs)} problems, {frames.sum()} frames in {time.perf_counter() - t0:.1f} s")
+    stream = torch.cuda.current_stream(dev)
+
+    def timed(fn, steps):
+        fn()
+        torch.cuda.synchronize()
+        evs = []
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            fn()
+            b.record(stream)
+            evs.append((a, b))
+        torch.cuda.synchronize()
+        wall = (time.perf_counter() - t0) / steps
+        return wall, float(np.median([a.elapsed_time(b) for a, b in evs]))
+
+    def fer(outs):
+        err = sum(int(np.any(o["hard"].cpu().numpy() != cw, axis=1).sum()) for o, cw in zip(outs, cws))
+        it = float(sum(int(o["iters"].sum()) for o in outs)) / frames.sum()
+        lo, hi = clopper_pearson(err, int(frames.sum()))
+        return dict(fer=err / frames.sum(), frame_errors=err, ci95=[lo, hi], mean_iters=it)
+
+    probs = [nd.Problem(c, x, p["max_iter"], want_post=False) for c, x, p in zip(codes, llrs, specs)]
+    t0 = time.perf_counter()
+    opts = autotune.tune_batch(probs, msg=rec["msg"], early_stop=rec["early_stop"],
+                               cache=args.tune_cache)
+    log(f"batched options {opts} ({time.perf_counter() - t0:.1f} s)")
+    batch = nd.Batch(probs, msg=rec["msg"], early_stop=rec["early_stop"], options=opts)
+    bwall, bms = timed(lambda: batch.launch(stream), args.batch_steps)
+    bstats = fer([p.out for p in probs])
+    info = batch.info
+    batch.close()
+
+    plain_out = [nd.new_outputs(p["frames"], c.n, dev, want_post=False) for p, c in zip(specs, codes)]
+
+    def plain():
+        for c, x, p, o in zip(codes, llrs, specs, plain_out):
+            nd.decode(c, x, p["max_iter"], early_stop=rec["early_stop"], msg="fp32", out=o, stream=stream)
+
+    pwall, pms = timed(plain, max(1, args.batch_steps // 2))
+    pstats = fer(plain_out)
+    for c in codes:
+        c.close()
+    return {
+        "workload": "256 QC problems, n in {576,1152,2304,4608}, R in {1/2,2/3,3/4}, z=n/24, "
+                    "64-1024 frames (log-uniform), Eb/N0 U[1,3] dB, 6-16 windows with overlap z/4, "
+                    "I_max 20, syndrome stop",
+        "frames": int(frames.sum()), "info_bits": bits,
+        "batched_fp16": {"gbit_s": bits / (bms * 1e-3) / 1e9, "ms": bms, "wall_ms": bwall * 1e3,
+                         "launches": info["num_launches"], "streams": info["num_streams"],
+                         "options": list(opts.as_tuple()), **bstats},
+        "plain_fp32_per_problem": {"gbit_s": bits / (pms * 1e-3) / 1e9, "ms": pms, "wall_ms": pwall * 1e3,
+                                   "launches": len(specs), **pstats},
+        "speedup": pms / bms,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -94,6 +180,9 @@ def main():
     ap.add_argument("--no-fp16", action="store_true", help="skip the FP16-message pass")
     ap.add_argument("--lanes", type=int, default=0, choices=[0, 1, 2],
                     help="lanes per CN visit for every message format (0: built-in choice)")
+    ap.add_argument("--no-batched", action="store_true", help="skip the mixed-batch leg")
+    ap.add_argument("--batch-steps", type=int, default=6)
+    ap.add_argument("--tune-cache", default=None, help="autotuner cache file (default: user cache dir)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device copy (for scaling HBM byte counters)")
     args = ap.parse_args()
@@ -204,6 +293,8 @@ def main():
         result["fp16_messages"] = {"gbit_s": bits / hwall / 1e9, "kernel_ms": hk,
                                    "lanes_per_cn": dcode.info["lanes_fp16"],
                                    "mean_iters": float(hiters.mean()), "fer": fer_table(hiters, hhard)}
+    if not args.no_batched:
+        result["batched"] = bench_batched(args, torch, nd, W, dev, log)
     if not args.no_cpu_baseline:
         import oracle
         groups = oracle.windows(code.m, *rec["windows"][:2], bool(rec["windows"][2]))

@@ -194,3 +194,17 @@ def test_single_decode_many_frames_per_workgroup_fixed_iterations():
         assert 0 < ok.sum() < len(ok)
         print("early stop", es, "decoded", ok.mean())
     dcode.close()
+
+
+def test_autotuner_picks_and_caches(mixed, tmp_path):
+    from paper_1202_1060_amd import autotune
+    probs = mixed.problems()
+    cache = str(tmp_path / "tune.json")
+    cands = [nd.BatchOptions(0, 1, 0, 4), nd.BatchOptions(1, 0, 256, 1), nd.BatchOptions(2, 1, 0, 2)]
+    best = autotune.tune_batch(probs, msg="fp16", cache=cache, candidates=cands, reps=2)
+    assert best.as_tuple() in [c.as_tuple() for c in cands]
+    again = autotune.tune_batch(probs, msg="fp16", cache=cache, candidates=[])
+    assert again.as_tuple() == best.as_tuple()
+    lanes = autotune.tune_code(mixed.codes[1], mixed.dllr[1], 20, msg="fp32", cache=cache, reps=2)
+    assert lanes in (1, 2) and mixed.codes[1].info["lanes_fp32"] == lanes
+    mixed.codes[1].tune("fp32", 0)
