@@ -167,6 +167,87 @@ def bench_batched(args, torch, nd, W, dev, log):
     }
 
 
+def bench_serving(args, torch, nd, W, dev, log):
+    """Serving over the three resident QC codes: saturated throughput of the
+    continuous-batching server, then Poisson arrivals at 0.5x and 0.8x of it
+    for the batched FP16 server and the per-request FP32 policy."""
+    from paper_1202_1060_amd.serve import Server, Requests
+    P = args.serve_pool
+    t0 = time.perf_counter()
+    codes, pools, cws, ks = [], [], [], []
+    for ci, (n, rate) in enumerate(W.SERVE_CODES):
+        key = W.qc_key(n, rate)
+        llr, cw = W.serve_pool(ci, P)
+        pools.append(torch.from_numpy(llr).to(dev))
+        cws.append(cw)
+        ks.append(W.encoder_for(key).k)
+        codes.append(nd.Code(W.CODES[key](), windows=W.serve_windows(n, rate)))
+    log(f"serving pools: {P} frames x {len(W.SERVE_BINS)} Eb/N0 points x 3 codes in "
+        f"{time.perf_counter() - t0:.1f} s")
+    N = args.serve_requests
+    r = W.serve_requests(count=N)
+    nvec = np.array([c.n for c in codes], dtype=np.int64)
+    kvec = np.array(ks, dtype=np.int64)
+    off = np.minimum((r["u"] * (P - r["frames"] + 1)).astype(np.int64), P - r["frames"])
+    base = np.array([p.data_ptr() for p in pools], dtype=np.uint64)
+    addr = base[r["code"]] + ((r["bin"] * P + off) * nvec[r["code"]] * 4).astype(np.uint64)
+    bits = r["frames"] * kvec[r["code"]]
+    max_iter = np.full(N, W.SERVE["max_iter"], dtype=np.int32)
+
+    def stream_at(rate, count):
+        arr = np.zeros(count) if rate is None else r["arrival"][:count] / rate
+        return Requests(arr, r["code"][:count], r["frames"][:count], addr[:count], max_iter[:count])
+
+    def fer(res, count):
+        err = 0
+        for i in range(count):
+            c, b, o, F = int(r["code"][i]), int(r["bin"][i]), int(off[i]), int(r["frames"][i])
+            err += int(np.any(res[i]["hard"] != cws[c][b, o:o + F], axis=1).sum())
+        tot = int(r["frames"][:count].sum())
+        lo, hi = clopper_pearson(err, tot)
+        return dict(fer=err / tot, frame_errors=err, frames=tot, ci95=[lo, hi])
+
+    batched = Server(codes, policy="batched", msg="fp16", budget_bytes=args.serve_budget,
+                     max_inflight=args.serve_inflight)
+    plain = Server(codes, policy="plain", budget_bytes=args.serve_budget)
+    # warm-up (allocator, kernels), then saturation: everything arrives at 0
+    batched.run(stream_at(None, min(N, 2000)))
+    plain.run(stream_at(None, 200))
+    sat = batched.run(stream_at(None, N))
+    sat_rate = N / sat["makespan"]
+    out = {"workload": "3 resident QC codes (n=648 R=5/6, n=1944 R=1/2, n=8064 R=1/2, z=n/24, one base row "
+                       "per window, overlap floor(z/4)); requests of 1-512 frames (geometric, mean 32), "
+                       "Eb/N0 U[1.5,3.5] dB, I_max 20, syndrome stop; request LLRs device-resident",
+           "requests": N, "frames": int(r["frames"].sum()),
+           "saturated": {"req_s": sat_rate, "gbit_s": float(bits.sum()) / sat["makespan"] / 1e9,
+                         "launches": sat["launches"], "p50_ms": sat["p50_ms"], "p99_ms": sat["p99_ms"]},
+           "loads": []}
+    log(f"serving saturated: {sat_rate:.0f} req/s, {out['saturated']['gbit_s']:.2f} Gbit/s")
+    for load in (0.5, 0.8):
+        rate = load * sat_rate
+        b = batched.run(stream_at(rate, N))
+        npl = min(N, args.serve_plain_requests)
+        p = plain.run(stream_at(rate, npl))
+        row = {"load": load, "offered_req_s": rate,
+               "batched_fp16": {"requests": N, "p50_ms": b["p50_ms"], "p99_ms": b["p99_ms"],
+                                "gbit_s": float(bits.sum()) / b["makespan"] / 1e9, "launches": b["launches"]},
+               "plain_fp32": {"requests": npl, "p50_ms": p["p50_ms"], "p99_ms": p["p99_ms"],
+                              "gbit_s": float(bits[:npl].sum()) / p["makespan"] / 1e9,
+                              "launches": p["launches"]}}
+        log(f"serving load {load}: batched p50 {b['p50_ms']:.2f} p99 {b['p99_ms']:.2f} ms; "
+            f"plain p50 {p['p50_ms']:.2f} p99 {p['p99_ms']:.2f} ms")
+        out["loads"].append(row)
+    # matched FER: outputs of both policies on the same requests (untimed)
+    nv = min(N, args.serve_verify)
+    vb = batched.run(stream_at(None, nv), keep_results=True)
+    vp = plain.run(stream_at(None, nv), keep_results=True)
+    out["fer_batched_fp16"] = fer(vb["results"], nv)
+    out["fer_plain_fp32"] = fer(vp["results"], nv)
+    for c in codes:
+        c.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -183,6 +264,13 @@ def main():
     ap.add_argument("--no-batched", action="store_true", help="skip the mixed-batch leg")
     ap.add_argument("--batch-steps", type=int, default=6)
     ap.add_argument("--tune-cache", default=None, help="autotuner cache file (default: user cache dir)")
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving leg")
+    ap.add_argument("--serve-requests", type=int, default=30000)
+    ap.add_argument("--serve-plain-requests", type=int, default=6000)
+    ap.add_argument("--serve-verify", type=int, default=2000)
+    ap.add_argument("--serve-pool", type=int, default=1024)
+    ap.add_argument("--serve-budget", type=int, default=2 << 30)
+    ap.add_argument("--serve-inflight", type=int, default=4)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device copy (for scaling HBM byte counters)")
     args = ap.parse_args()
@@ -295,6 +383,8 @@ def main():
                                    "mean_iters": float(hiters.mean()), "fer": fer_table(hiters, hhard)}
     if not args.no_batched:
         result["batched"] = bench_batched(args, torch, nd, W, dev, log)
+    if not args.no_serving:
+        result["serving"] = bench_serving(args, torch, nd, W, dev, log)
     if not args.no_cpu_baseline:
         import oracle
         groups = oracle.windows(code.m, *rec["windows"][:2], bool(rec["windows"][2]))

@@ -200,8 +200,13 @@ int ldpc_batch_query(ldpc_batch_t batch, ldpc_batch_info* info);
 /* The caller guarantees that no enqueued launch still uses the batch. */
 int ldpc_batch_destroy(ldpc_batch_t batch);
 
-/* One-shot form: create with default options, launch on hip_stream, wait
- * for hip_stream to finish, destroy. Returns after the decode is done. */
+/* One-shot form with default options, asynchronous on hip_stream like
+ * ldpc_decode: the problem table is staged through a per-device ring of 16
+ * pinned-host/device slots that the library keeps for the life of the
+ * process, so a call allocates nothing once its slot is large enough (the
+ * 17th call in flight waits on the host for the 1st to finish). At most 64
+ * launch classes per call. Not for graph capture (use ldpc_batch_launch).
+ * Errors: as ldpc_batch_create, plus EUNSUPPORTED for too many classes. */
 int ldpc_decode_batched(const ldpc_problem* probs, int32_t count, uint32_t flags, void* hip_stream);
 
 /* Message of the last failed call on this thread ("" if none). */

@@ -123,22 +123,38 @@ def serve_windows(n: int, rate: str):
     return (base_rows(rate), (n // 24) // 4, 1)
 
 
-def serve_requests(recipe: dict = SERVE, count: int = 256, rate_per_s: float = 1000.0):
-    """Request stream of the serving workload: dicts with arrival time (s,
-    Poisson at ``rate_per_s``), code key, frames, Eb/N0 and frame seed."""
+SERVE_BINS = np.round(np.arange(1.5, 3.5 + 1e-9, 0.25), 2)  # Eb/N0 grid of the frame pools
+
+
+def serve_requests(recipe: dict = SERVE, count: int = 256):
+    """Request stream of the serving workload at unit offered load (one
+    request per second on average; scale ``arrival`` by 1/rate). Arrays:
+    arrival (Poisson process), code (index into SERVE_CODES), frames
+    (geometric, mean 32, at most 512), ebn0 (uniform), bin (nearest point of
+    SERVE_BINS) and pool offset (uniform, so the request's frames are pool
+    frames offset .. offset + frames - 1 of its code and bin)."""
     rng = _philox(recipe["seed"], 0)
-    t = 0.0
-    out = []
-    p = 1.0 / recipe["mean_frames"]
-    for i in range(count):
-        t += float(rng.exponential(1.0 / rate_per_s))
-        n, rate = SERVE_CODES[rng.integers(len(SERVE_CODES))]
-        F = int(min(recipe["max_frames"], rng.geometric(p)))
-        eb = float(rng.uniform(*recipe["ebn0"]))
-        out.append(dict(index=i, arrival=t, code=qc_key(n, rate), n=n, rate=rate,
-                        windows=serve_windows(n, rate), frames=F, ebn0=eb,
-                        max_iter=recipe["max_iter"], seed=recipe["seed"] * 1000 + 1 + i))
-    return out
+    arrival = np.cumsum(rng.exponential(1.0, size=count))
+    code = rng.integers(len(SERVE_CODES), size=count)
+    frames = np.minimum(recipe["max_frames"], rng.geometric(1.0 / recipe["mean_frames"], size=count))
+    ebn0 = rng.uniform(*recipe["ebn0"], size=count)
+    b = np.clip(np.round((ebn0 - SERVE_BINS[0]) / 0.25).astype(np.int64), 0, len(SERVE_BINS) - 1)
+    u = rng.random(count)
+    return dict(arrival=arrival, code=code, frames=frames.astype(np.int64), ebn0=ebn0, bin=b, u=u)
+
+
+def serve_pool(code_index: int, frames_per_bin: int, recipe: dict = SERVE):
+    """Frame pool of one serving code: LLRs (bins, frames_per_bin, n) and
+    codewords, random information bits, one seeded stream per bin."""
+    n, rate = SERVE_CODES[code_index]
+    key = qc_key(n, rate)
+    enc = encoder_for(key)
+    llr = np.empty((len(SERVE_BINS), frames_per_bin, n), dtype=np.float32)
+    cw = np.empty((len(SERVE_BINS), frames_per_bin, n), dtype=np.uint8)
+    for i, eb in enumerate(SERVE_BINS):
+        llr[i], cw[i] = make_frames(n, frames_per_bin, float(eb), enc.rate,
+                                    recipe["seed"] * 1000 + 100 * code_index + i, encoder=enc)
+    return llr, cw
 
 
 def problem_frames(prob: dict, num_frames: int | None = None):

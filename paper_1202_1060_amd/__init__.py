@@ -271,7 +271,8 @@ class Batch:
 
 
 def decode_batched(problems, *, msg="fp16", early_stop=True, stream=None):
-    """One-shot batched decode (ldpc_decode_batched): returns when done."""
+    """One-shot batched decode (ldpc_decode_batched), asynchronous on
+    ``stream``; returns the problems' output dicts."""
     flags = msg_flag(msg) | (LDPC_FLAG_EARLY_STOP if early_stop else 0)
     dev = problems[0].llr.device if problems else torch.device("cuda", 0)
     s = stream if stream is not None else torch.cuda.current_stream(dev)

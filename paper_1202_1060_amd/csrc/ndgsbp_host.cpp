@@ -6,6 +6,8 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -306,6 +308,216 @@ void free_batch(ldpc_batch* b) {
     b->work = nullptr;
 }
 
+int check_options(const ldpc_batch_options& o) {
+    if (o.lanes_per_cn < 0 || o.lanes_per_cn > 2) return fail(LDPC_EINVAL, "lanes_per_cn must be 0, 1 or 2");
+    if (o.max_threads < 0 || o.max_threads % 64 || o.max_threads > 1024)
+        return fail(LDPC_EINVAL, "max_threads must be 0 or a multiple of 64 up to 1024");
+    if (o.streams < 0 || o.streams > kMaxBatchStreams) return fail(LDPC_EINVAL, "streams must be in 0..8");
+    return LDPC_OK;
+}
+
+// Launch classes of a set of problems (validated), their problem table in
+// class order, and the device they run on.
+struct ClassPlan {
+    std::vector<BatchClass> classes;
+    std::vector<Problem> table;
+    int32_t device = -1;
+    int num_cus = 0;
+    int64_t total_frames = 0;
+};
+
+int form_classes(const ldpc_problem* probs, int32_t count, MsgKind kind, const ldpc_batch_options& o,
+                 ClassPlan& plan) {
+    if (count < 0) return fail(LDPC_EINVAL, "count < 0");
+    if (count > 0 && !probs) return fail(LDPC_EINVAL, "probs is NULL");
+    struct Item {
+        int idx;
+        const Layout* lay;
+        ClassKey key;
+        size_t lds;
+        int threads;
+    };
+    std::vector<Item> items;
+    for (int i = 0; i < count; ++i) {
+        const ldpc_problem& q = probs[i];
+        const std::string at = "problem " + std::to_string(i) + ": ";
+        if (!q.code) return fail(LDPC_EINVAL, at + "code is NULL");
+        if (q.num_frames < 0) return fail(LDPC_EINVAL, at + "num_frames < 0");
+        if (q.max_iter < 1) return fail(LDPC_EINVAL, at + "max_iter < 1");
+        if (plan.device < 0) {
+            plan.device = q.code->device;
+            plan.num_cus = q.code->num_cus;
+        } else if (q.code->device != plan.device) {
+            return fail(LDPC_EINVAL, at + "codes of one batch must be on one device");
+        }
+        if (q.num_frames == 0) continue;
+        if (!q.llr || !q.hard || !q.iters) return fail(LDPC_EINVAL, at + "llr, hard and iters are required");
+        const int h = o.lanes_per_cn ? o.lanes_per_cn : q.code->lanes_for[kind];
+        const Layout& lay = q.code->lay[h - 1];
+        if (!lay.valid) return fail(LDPC_EUNSUPPORTED, at + "no kernel variant with that mapping");
+        int rc = check_lds(q.code, lay, kind);
+        if (rc) return fail(rc, at + g_last_error);
+        Item it;
+        it.idx = i;
+        it.lay = &lay;
+        it.lds = lds_bytes(q.code, lay, kind);
+        it.threads = threads_for(q.code, lay);
+        it.key.D = lay.D;
+        it.key.H = lay.H;
+        it.key.uniform = lay.uniform;
+        it.key.size_class = o.split_by_size ? size_class(it.lds) : 0;
+        items.push_back(it);
+    }
+    // classes: one persistent launch each
+    std::stable_sort(items.begin(), items.end(), [](const Item& x, const Item& y) { return x.key < y.key; });
+    for (size_t s = 0; s < items.size();) {
+        size_t e = s;
+        while (e < items.size() && !(items[s].key < items[e].key) && !(items[e].key < items[s].key)) ++e;
+        BatchClass bc;
+        bc.key = items[s].key;
+        bc.table_offset = (int32_t)plan.table.size();
+        size_t lds = 0;
+        int threads = 64;
+        int64_t frames = 0;
+        double work = 0.0;
+        for (size_t k = s; k < e; ++k) {
+            const ldpc_problem& q = probs[items[k].idx];
+            if (frames + q.num_frames > INT32_MAX)
+                return fail(LDPC_EUNSUPPORTED, "more than 2^31 - 1 frames in one launch class");
+            plan.table.push_back(make_problem(q.code, *items[k].lay, q.llr, q.num_frames, q.max_iter, q.hard,
+                                              q.post, q.iters, q.syn_ok));
+            plan.table.back().first = (int32_t)frames;
+            frames += q.num_frames;
+            work += (double)q.num_frames * (double)q.code->edge_updates * q.max_iter;
+            lds = std::max(lds, items[k].lds);
+            threads = std::max(threads, items[k].threads);
+        }
+        if (o.max_threads) threads = std::min(threads, o.max_threads);
+        bc.nprob = (int32_t)(e - s);
+        bc.total_frames = (int32_t)frames;
+        bc.work_estimate = work;
+        bc.shape.lanes = bc.key.H;
+        bc.shape.threads = threads;
+        bc.shape.lds_bytes = lds;
+        plan.total_frames += frames;
+        plan.classes.push_back(bc);
+        s = e;
+    }
+    // the longest launches first, so that short ones fill the tails
+    std::stable_sort(plan.classes.begin(), plan.classes.end(),
+                     [](const BatchClass& x, const BatchClass& y) { return x.work_estimate > y.work_estimate; });
+    return LDPC_OK;
+}
+
+void finish_class_args(BatchClass& bc, const std::vector<Problem>& table, const Problem* dev_table, uint32_t* work,
+                       uint32_t flags) {
+    DecodeArgs& a = bc.args;
+    a = DecodeArgs{};
+    a.p0 = table[bc.table_offset];
+    a.table = dev_table + bc.table_offset;
+    a.nprob = bc.nprob;
+    a.total_frames = bc.total_frames;
+    a.work = work;
+    set_launch_constants(a, flags, bc.shape.lds_bytes);
+}
+
+// Enqueues the classes: class k on stream k mod S of {main, extra...}, the
+// extra streams forked from and joined back into `main` with evs[0] (fork)
+// and evs[1..] (joins); evs holds extra.size() + 1 events.
+hipError_t launch_classes(const std::vector<BatchClass>& classes, MsgKind kind, hipStream_t main,
+                          const std::vector<hipStream_t>& extra, const std::vector<hipEvent_t>& evs) {
+    const int ns = (int)extra.size() + 1;
+    hipError_t e = hipSuccess;
+    if (ns > 1) {
+        e = hipEventRecord(evs[0], main);
+        for (int k = 1; k < ns && e == hipSuccess; ++k) e = hipStreamWaitEvent(extra[k - 1], evs[0], 0);
+    }
+    for (size_t k = 0; k < classes.size() && e == hipSuccess; ++k) {
+        const BatchClass& bc = classes[k];
+        hipStream_t st = k % ns == 0 ? main : extra[k % ns - 1];
+        e = launch_decode(bc.args, kind, bc.key.D, bc.key.uniform, bc.shape, st);
+    }
+    for (int k = 1; k < ns && e == hipSuccess; ++k) {
+        e = hipEventRecord(evs[k], extra[k - 1]);
+        if (e == hipSuccess) e = hipStreamWaitEvent(main, evs[k], 0);
+    }
+    return e;
+}
+
+// Staging ring of the asynchronous ldpc_decode_batched, one per device, kept
+// for the life of the process: each slot holds a pinned host and a device
+// copy of a problem table, work counters and fork/join events; a slot is
+// reused once the call that last used it has finished on the device.
+constexpr int kStageRing = 16;
+constexpr int kStageClasses = 64;
+constexpr int kStageStreams = 4;
+
+struct StageSlot {
+    Problem* host = nullptr;  // pinned
+    Problem* dev = nullptr;
+    size_t cap = 0;           // problems
+    uint32_t* work = nullptr; // 2 per class, zero between launches
+    hipEvent_t done = nullptr;
+    std::vector<hipEvent_t> fork_join;
+    bool in_use = false;
+};
+
+struct DeviceStage {
+    std::mutex mu;
+    StageSlot slots[kStageRing];
+    unsigned next = 0;
+    std::vector<hipStream_t> streams;  // kStageStreams - 1 extra streams
+};
+
+std::mutex g_stage_mu;
+std::map<int, DeviceStage*> g_stage;
+
+hipError_t get_stage(int device, DeviceStage** out) {
+    std::lock_guard<std::mutex> lock(g_stage_mu);
+    auto it = g_stage.find(device);
+    if (it != g_stage.end()) {
+        *out = it->second;
+        return hipSuccess;
+    }
+    DeviceStage* ds = new DeviceStage();
+    hipError_t e = hipSuccess;
+    for (int k = 1; k < kStageStreams && e == hipSuccess; ++k) {
+        hipStream_t st = nullptr;
+        e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
+        if (e == hipSuccess) ds->streams.push_back(st);
+    }
+    for (StageSlot& s : ds->slots) {
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&s.done, hipEventDisableTiming);
+        for (int k = 0; k < kStageStreams && e == hipSuccess; ++k) {
+            hipEvent_t ev = nullptr;
+            e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+            if (e == hipSuccess) s.fork_join.push_back(ev);
+        }
+        if (e == hipSuccess) e = hipMalloc((void**)&s.work, 2 * sizeof(uint32_t) * kStageClasses);
+        if (e == hipSuccess) e = hipMemset(s.work, 0, 2 * sizeof(uint32_t) * kStageClasses);
+    }
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e != hipSuccess) return e;  // the partial ring is leaked; the call fails
+    g_stage[device] = ds;
+    *out = ds;
+    return hipSuccess;
+}
+
+// Grows a slot's tables to hold `n` problems (allocates only on growth).
+hipError_t reserve_slot(StageSlot& s, size_t n) {
+    if (n <= s.cap) return hipSuccess;
+    size_t cap = std::max<size_t>(n, 2 * s.cap);
+    (void)hipHostFree(s.host);
+    (void)hipFree(s.dev);
+    s.host = nullptr;
+    s.dev = nullptr;
+    s.cap = 0;
+    hipError_t e = hipHostMalloc((void**)&s.host, cap * sizeof(Problem), hipHostMallocDefault);
+    if (e == hipSuccess) e = hipMalloc((void**)&s.dev, cap * sizeof(Problem));
+    if (e == hipSuccess) s.cap = cap;
+    return e;
+}
+
 }  // namespace
 
 extern "C" {
@@ -584,128 +796,41 @@ int ldpc_batch_create(const ldpc_problem* probs, int32_t count, uint32_t flags, 
     g_last_error.clear();
     if (!out) return fail(LDPC_EINVAL, "out is NULL");
     *out = nullptr;
-    if (count < 0) return fail(LDPC_EINVAL, "count < 0");
-    if (count > 0 && !probs) return fail(LDPC_EINVAL, "probs is NULL");
     int rc = check_flags(flags);
     if (rc) return rc;
     ldpc_batch_options o = default_batch_options();
     if (opt) o = *opt;
-    if (o.lanes_per_cn < 0 || o.lanes_per_cn > 2) return fail(LDPC_EINVAL, "lanes_per_cn must be 0, 1 or 2");
-    if (o.max_threads < 0 || o.max_threads % 64 || o.max_threads > 1024)
-        return fail(LDPC_EINVAL, "max_threads must be 0 or a multiple of 64 up to 1024");
-    if (o.streams < 0 || o.streams > kMaxBatchStreams) return fail(LDPC_EINVAL, "streams must be in 0..8");
+    rc = check_options(o);
+    if (rc) return rc;
     const MsgKind kind = msg_kind(flags);
-
-    // validate; pick each problem's mapping and class
-    struct Item {
-        int idx;
-        const Layout* lay;
-        ClassKey key;
-        size_t lds;
-        int threads;
-    };
-    std::vector<Item> items;
-    int32_t device = -1;
-    int num_cus = 0;
-    size_t max_lds = 0;
-    for (int i = 0; i < count; ++i) {
-        const ldpc_problem& q = probs[i];
-        const std::string at = "problem " + std::to_string(i) + ": ";
-        if (!q.code) return fail(LDPC_EINVAL, at + "code is NULL");
-        if (q.num_frames < 0) return fail(LDPC_EINVAL, at + "num_frames < 0");
-        if (q.max_iter < 1) return fail(LDPC_EINVAL, at + "max_iter < 1");
-        if (device < 0) {
-            device = q.code->device;
-            num_cus = q.code->num_cus;
-            max_lds = q.code->max_lds;
-        } else if (q.code->device != device) {
-            return fail(LDPC_EINVAL, at + "codes of one batch must be on one device");
-        }
-        if (q.num_frames == 0) continue;
-        if (!q.llr || !q.hard || !q.iters) return fail(LDPC_EINVAL, at + "llr, hard and iters are required");
-        const int h = o.lanes_per_cn ? o.lanes_per_cn : q.code->lanes_for[kind];
-        const Layout& lay = q.code->lay[h - 1];
-        if (!lay.valid) return fail(LDPC_EUNSUPPORTED, at + "no kernel variant with that mapping");
-        rc = check_lds(q.code, lay, kind);
-        if (rc) return fail(rc, at + g_last_error);
-        Item it;
-        it.idx = i;
-        it.lay = &lay;
-        it.lds = lds_bytes(q.code, lay, kind);
-        it.threads = threads_for(q.code, lay);
-        it.key.D = lay.D;
-        it.key.H = lay.H;
-        it.key.uniform = lay.uniform;
-        it.key.size_class = o.split_by_size ? size_class(it.lds) : 0;
-        items.push_back(it);
-    }
+    ClassPlan plan;
+    rc = form_classes(probs, count, kind, o, plan);
+    if (rc) return rc;
 
     ldpc_batch* b = new (std::nothrow) ldpc_batch();
     if (!b) return fail(LDPC_ENOMEM, "host allocation failed");
-    b->device = device;
+    b->device = plan.device;
     b->kind = kind;
     b->num_problems = count;
-
-    // classes: one persistent launch each
-    std::stable_sort(items.begin(), items.end(), [](const Item& x, const Item& y) { return x.key < y.key; });
-    std::vector<Problem> table;
-    for (size_t s = 0; s < items.size();) {
-        size_t e = s;
-        while (e < items.size() && !(items[s].key < items[e].key) && !(items[e].key < items[s].key)) ++e;
-        BatchClass bc;
-        bc.key = items[s].key;
-        bc.table_offset = (int32_t)table.size();
-        size_t lds = 0;
-        int threads = 64;
-        int64_t frames = 0;
-        double work = 0.0;
-        for (size_t k = s; k < e; ++k) {
-            const ldpc_problem& q = probs[items[k].idx];
-            if (frames + q.num_frames > INT32_MAX) {
-                delete b;
-                return fail(LDPC_EUNSUPPORTED, "more than 2^31 - 1 frames in one launch class");
-            }
-            table.push_back(make_problem(q.code, *items[k].lay, q.llr, q.num_frames, q.max_iter, q.hard, q.post,
-                                         q.iters, q.syn_ok));
-            table.back().first = (int32_t)frames;
-            frames += q.num_frames;
-            work += (double)q.num_frames * (double)q.code->edge_updates * q.max_iter;
-            lds = std::max(lds, items[k].lds);
-            threads = std::max(threads, items[k].threads);
-        }
-        if (o.max_threads) threads = std::min(threads, o.max_threads);
-        bc.nprob = (int32_t)(e - s);
-        bc.total_frames = (int32_t)frames;
-        bc.work_estimate = work;
-        bc.shape.lanes = bc.key.H;
-        bc.shape.threads = threads;
-        bc.shape.lds_bytes = lds;
-        b->total_frames += frames;
-        b->classes.push_back(bc);
-        s = e;
-    }
-    // the longest launches first, so that short ones fill the tails
-    std::stable_sort(b->classes.begin(), b->classes.end(),
-                     [](const BatchClass& x, const BatchClass& y) { return x.work_estimate > y.work_estimate; });
-
+    b->total_frames = plan.total_frames;
+    b->classes = std::move(plan.classes);
     if (b->classes.empty()) {
         *out = b;
         return LDPC_OK;
     }
-    DeviceGuard guard(device);
+    DeviceGuard guard(b->device);
     if (!guard.ok) {
         delete b;
         return fail(LDPC_EHIP, "cannot select the batch's device");
     }
-    (void)max_lds;
     for (BatchClass& bc : b->classes) {
-        rc = set_blocks(kind, bc.key.D, bc.key.uniform, true, num_cus, bc.total_frames, bc.shape);
+        rc = set_blocks(kind, bc.key.D, bc.key.uniform, true, plan.num_cus, bc.total_frames, bc.shape);
         if (rc) {
             delete b;
             return rc;
         }
     }
-    hipError_t e = upload(&b->table, table);
+    hipError_t e = upload(&b->table, plan.table);
     if (e == hipSuccess) e = hipMalloc((void**)&b->work, 2 * sizeof(uint32_t) * b->classes.size());
     if (e == hipSuccess) e = hipMemset(b->work, 0, 2 * sizeof(uint32_t) * b->classes.size());
     const int nstreams = std::min<int>(std::max(1, o.streams), (int)b->classes.size());
@@ -725,17 +850,8 @@ int ldpc_batch_create(const ldpc_problem* probs, int32_t count, uint32_t flags, 
         delete b;
         return hip_fail(e, "batch tables");
     }
-    for (size_t k = 0; k < b->classes.size(); ++k) {
-        BatchClass& bc = b->classes[k];
-        DecodeArgs& a = bc.args;
-        a = DecodeArgs{};
-        a.p0 = table[bc.table_offset];
-        a.table = b->table + bc.table_offset;
-        a.nprob = bc.nprob;
-        a.total_frames = bc.total_frames;
-        a.work = b->work + 2 * k;
-        set_launch_constants(a, flags, bc.shape.lds_bytes);
-    }
+    for (size_t k = 0; k < b->classes.size(); ++k)
+        finish_class_args(b->classes[k], plan.table, b->table, b->work + 2 * k, flags);
     *out = b;
     return LDPC_OK;
 }
@@ -756,24 +872,7 @@ int ldpc_batch_launch(ldpc_batch_t b, void* hip_stream) {
     if (b->classes.empty()) return LDPC_OK;
     DeviceGuard guard(b->device);
     if (!guard.ok) return fail(LDPC_EHIP, "cannot select the batch's device");
-    hipStream_t main = (hipStream_t)hip_stream;
-    const int ns = (int)b->streams.size() + 1;
-    hipError_t e = hipSuccess;
-    if (ns > 1) {
-        // fork: the other streams start after the work already on `main`
-        e = hipEventRecord(b->events[0], main);
-        for (int k = 1; k < ns && e == hipSuccess; ++k) e = hipStreamWaitEvent(b->streams[k - 1], b->events[0], 0);
-    }
-    for (size_t k = 0; k < b->classes.size() && e == hipSuccess; ++k) {
-        const BatchClass& bc = b->classes[k];
-        hipStream_t st = k % ns == 0 ? main : b->streams[k % ns - 1];
-        e = launch_decode(bc.args, b->kind, bc.key.D, bc.key.uniform, bc.shape, st);
-    }
-    // join: `main` continues after every launch
-    for (int k = 1; k < ns && e == hipSuccess; ++k) {
-        e = hipEventRecord(b->events[k], b->streams[k - 1]);
-        if (e == hipSuccess) e = hipStreamWaitEvent(main, b->events[k], 0);
-    }
+    hipError_t e = launch_classes(b->classes, b->kind, (hipStream_t)hip_stream, b->streams, b->events);
     if (e != hipSuccess) return hip_fail(e, "batch launch");
     return LDPC_OK;
 }
@@ -790,19 +889,48 @@ int ldpc_batch_destroy(ldpc_batch_t b) {
 }
 
 int ldpc_decode_batched(const ldpc_problem* probs, int32_t count, uint32_t flags, void* hip_stream) {
-    ldpc_batch_t b = nullptr;
-    int rc = ldpc_batch_create(probs, count, flags, nullptr, &b);
+    g_last_error.clear();
+    int rc = check_flags(flags);
     if (rc) return rc;
-    rc = ldpc_batch_launch(b, hip_stream);
-    if (rc == LDPC_OK && !b->classes.empty()) {
-        DeviceGuard guard(b->device);
-        hipError_t e = hipStreamSynchronize((hipStream_t)hip_stream);
-        if (e != hipSuccess) rc = hip_fail(e, "batched decode");
+    const MsgKind kind = msg_kind(flags);
+    const ldpc_batch_options o = default_batch_options();
+    ClassPlan plan;
+    rc = form_classes(probs, count, kind, o, plan);
+    if (rc) return rc;
+    if (plan.classes.empty()) return LDPC_OK;
+    if (plan.classes.size() > (size_t)kStageClasses)
+        return fail(LDPC_EUNSUPPORTED, "more than " + std::to_string(kStageClasses) + " launch classes in one call");
+    DeviceGuard guard(plan.device);
+    if (!guard.ok) return fail(LDPC_EHIP, "cannot select the problems' device");
+    for (BatchClass& bc : plan.classes) {
+        rc = set_blocks(kind, bc.key.D, bc.key.uniform, true, plan.num_cus, bc.total_frames, bc.shape);
+        if (rc) return rc;
     }
-    std::string msg = g_last_error;
-    ldpc_batch_destroy(b);
-    g_last_error = msg;
-    return rc;
+    DeviceStage* ds = nullptr;
+    hipError_t e = get_stage(plan.device, &ds);
+    if (e != hipSuccess) return hip_fail(e, "staging ring");
+    hipStream_t main = (hipStream_t)hip_stream;
+    std::lock_guard<std::mutex> lock(ds->mu);
+    StageSlot& slot = ds->slots[ds->next++ % kStageRing];
+    // the slot's previous call must be done with its buffers
+    if (slot.in_use) {
+        e = hipEventSynchronize(slot.done);
+        if (e != hipSuccess) return hip_fail(e, "staging slot wait");
+    }
+    e = reserve_slot(slot, plan.table.size());
+    if (e != hipSuccess) return hip_fail(e, "staging slot");
+    std::memcpy(slot.host, plan.table.data(), plan.table.size() * sizeof(Problem));
+    e = hipMemcpyAsync(slot.dev, slot.host, plan.table.size() * sizeof(Problem), hipMemcpyHostToDevice, main);
+    for (size_t k = 0; k < plan.classes.size(); ++k)
+        finish_class_args(plan.classes[k], plan.table, slot.dev, slot.work + 2 * k, flags);
+    const int ns = std::min<int>(kStageStreams, (int)plan.classes.size());
+    std::vector<hipStream_t> extra(ds->streams.begin(), ds->streams.begin() + (ns - 1));
+    std::vector<hipEvent_t> evs(slot.fork_join.begin(), slot.fork_join.begin() + ns);
+    if (e == hipSuccess) e = launch_classes(plan.classes, kind, main, extra, evs);
+    if (e == hipSuccess) e = hipEventRecord(slot.done, main);
+    slot.in_use = true;
+    if (e != hipSuccess) return hip_fail(e, "batched decode");
+    return LDPC_OK;
 }
 
 }  // extern "C"

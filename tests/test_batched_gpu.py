@@ -208,3 +208,26 @@ def test_autotuner_picks_and_caches(mixed, tmp_path):
     lanes = autotune.tune_code(mixed.codes[1], mixed.dllr[1], 20, msg="fp32", cache=cache, reps=2)
     assert lanes in (1, 2) and mixed.codes[1].info["lanes_fp32"] == lanes
     mixed.codes[1].tune("fp32", 0)
+
+
+def test_async_batched_calls_in_flight(mixed):
+    """40 asynchronous ldpc_decode_batched calls (more than the 16 staging
+    slots) on two streams without host synchronisation, each on a different
+    subset of the problems with its own outputs: every output equals the
+    single decode of its problem."""
+    rng = np.random.default_rng(3)
+    streams = [torch.cuda.current_stream(), torch.cuda.Stream()]
+    streams[1].wait_stream(streams[0])
+    calls = []
+    for c in range(40):
+        idx = sorted(rng.choice(len(mixed.specs), size=int(rng.integers(1, 6)), replace=False).tolist())
+        probs = [nd.Problem(mixed.codes[i], mixed.dllr[i], mixed.specs[i]["max_iter"]) for i in idx]
+        nd.decode_batched(probs, msg="fp16", stream=streams[c % 2])
+        calls.append((idx, probs))
+    torch.cuda.synchronize()
+    want = {i: _single(mixed, i, "fp16") for i in range(len(mixed.specs))}
+    for idx, probs in calls:
+        for i, p in zip(idx, probs):
+            got = _host(p.out)
+            for k in want[i]:
+                assert np.array_equal(got[k], want[i][k]), (idx, i, k)

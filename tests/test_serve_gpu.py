@@ -1,0 +1,93 @@
+"""Serving with continuous batching (paper_1202_1060_amd.serve) on the GPU.
+
+Each request's result must be the same whether it is decoded alone or
+served in the mix of requests the server batched it with: bit for bit,
+since a frame's arithmetic does not depend on its neighbours.
+"""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover - GPU machine only
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+import paper_1202_1060_amd as nd  # noqa: E402
+from paper_1202_1060_amd.serve import Server, Requests  # noqa: E402
+from ldpcgen import workloads as W  # noqa: E402
+
+from parity import gpu_decode, syndrome_zero  # noqa: E402
+
+DEV = torch.device("cuda:0")
+P = 160  # pool frames per code and Eb/N0 point
+
+
+@pytest.fixture(scope="module")
+def setup():
+    codes, pools, hcodes = [], [], []
+    for ci, (n, rate) in enumerate(W.SERVE_CODES):
+        key = W.qc_key(n, rate)
+        llr, _ = W.serve_pool(ci, P)
+        pools.append((llr, torch.from_numpy(llr).to(DEV)))
+        hcodes.append(W.CODES[key]())
+        codes.append(nd.Code(hcodes[-1], windows=W.serve_windows(n, rate)))
+    r = W.serve_requests(count=240)
+    r["frames"] = np.minimum(r["frames"], 48)
+    off = np.minimum((r["u"] * (P - r["frames"] + 1)).astype(np.int64), P - r["frames"])
+    nvec = np.array([c.n for c in codes], dtype=np.int64)
+    base = np.array([p[1].data_ptr() for p in pools], dtype=np.uint64)
+    addr = base[r["code"]] + ((r["bin"] * P + off) * nvec[r["code"]] * 4).astype(np.uint64)
+    yield dict(codes=codes, hcodes=hcodes, pools=pools, r=r, off=off, addr=addr)
+    for c in codes:
+        c.close()
+
+
+def _stream(s, count, rate):
+    r = s["r"]
+    arr = np.zeros(count) if rate is None else r["arrival"][:count] / rate
+    return Requests(arr, r["code"][:count], r["frames"][:count], s["addr"][:count],
+                    np.full(count, 20, dtype=np.int32))
+
+
+def _alone(s, i, msg):
+    r = s["r"]
+    c, b, o, F = int(r["code"][i]), int(r["bin"][i]), int(s["off"][i]), int(r["frames"][i])
+    llr = s["pools"][c][0][b, o:o + F]
+    return gpu_decode(s["codes"][c], llr, 20, True, msg)
+
+
+@pytest.mark.parametrize("policy,rate", [("batched", None), ("batched", 20000.0), ("plain", 20000.0)])
+def test_served_equals_alone(setup, policy, rate):
+    msg = "fp16" if policy == "batched" else "fp32"
+    srv = Server(setup["codes"], policy=policy, msg=msg, budget_bytes=64 << 20, max_inflight=3)
+    out = srv.run(_stream(setup, 240, rate), keep_results=True)
+    print(policy, rate, "launches", out["launches"], "p50", out["p50_ms"], "p99", out["p99_ms"])
+    if policy == "batched" and rate is None:
+        assert out["launches"] < 240  # requests were batched together
+    assert np.all(out["latency"] >= 0)
+    for i in range(240):
+        got = out["results"][i]
+        want = _alone(setup, i, msg)
+        for k in ("hard", "iters", "syn_ok"):
+            assert np.array_equal(got[k], want[k]), (i, k)
+        code = setup["hcodes"][int(setup["r"]["code"][i])]
+        assert np.array_equal(got["syn_ok"].astype(bool), syndrome_zero(code, got["hard"])), i
+
+
+def test_admission_by_device_memory(setup):
+    """A budget that holds only a few requests at a time still serves them
+    all, correctly; a request larger than the budget is refused."""
+    s = setup
+    budget = 2 * 48 * (8064 + 5)
+    srv = Server(s["codes"], policy="batched", budget_bytes=budget, max_inflight=4)
+    req = _stream(s, 60, None)
+    out = srv.run(req, keep_results=True)
+    # every launch holds at most the budget
+    assert out["launches"] >= int(np.ceil(srv.request_bytes(req).sum() / budget)) > 1
+    for i in range(60):
+        want = _alone(s, i, "fp16")
+        assert np.array_equal(out["results"][i]["hard"], want["hard"]), i
+    tiny = Server(s["codes"], policy="batched", budget_bytes=1000)
+    with pytest.raises(ValueError):
+        tiny.run(_stream(s, 10, None))
