@@ -41,6 +41,7 @@ extern "C" {
 #define LDPC_FLAG_EARLY_STOP 0x1u /* stop a frame at its first zero syndrome (Step 4b) */
 #define LDPC_FLAG_MSG_FP16 0x2u   /* store CN->VN messages as IEEE binary16           */
 #define LDPC_FLAG_MSG_BF16 0x4u   /* store CN->VN messages as bfloat16                */
+#define LDPC_FLAG_OUT_PACKED 0x8u /* hard decisions 8 per byte: see ldpc_decode        */
 
 typedef struct ldpc_code* ldpc_code_t;
 
@@ -116,7 +117,9 @@ int ldpc_code_tune(ldpc_code_t code, uint32_t msg_flags, int32_t lanes_per_cn);
 
 /* Decode num_frames frames (Sec. II-C, Steps 2-4).
  *   llr    device, float [num_frames][n]: channel LLRs L_n = 2 y_n / sigma^2
- *   hard   device, uint8 [num_frames][n]: d_n = 1 iff total LLR < 0 (Step 4a)
+ *   hard   device, uint8 [num_frames][n]: d_n = 1 iff total LLR < 0 (Step 4a);
+ *          with LDPC_FLAG_OUT_PACKED uint8 [num_frames][(n + 7) / 8], bit k of
+ *          byte q = d_{8q+k}, bits past n zero
  *   post   device, float [num_frames][n]: total LLR of eq. (3), or NULL
  *   iters  device, int32 [num_frames]: iterations run, in [1, max_iter]
  *   syn_ok device, uint8 [num_frames]: 1 iff D H^T = 0 at the end, or NULL

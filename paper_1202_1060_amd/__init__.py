@@ -16,14 +16,15 @@ import torch  # noqa: F401  (must precede loading the library)
 from . import _native
 from ._native import (LdpcError, LDPC_OK, LDPC_EINVAL, LDPC_ENOMEM, LDPC_EHIP,
                       LDPC_EUNSUPPORTED, LDPC_GROUPS_WINDOWS, LDPC_GROUPS_EXPLICIT,
-                      LDPC_FLAG_EARLY_STOP, LDPC_FLAG_MSG_FP16, LDPC_FLAG_MSG_BF16)
+                      LDPC_FLAG_EARLY_STOP, LDPC_FLAG_MSG_FP16, LDPC_FLAG_MSG_BF16,
+                      LDPC_FLAG_OUT_PACKED)
 
 __all__ = [
     "Code", "ldpc_code_create", "ldpc_code_destroy", "ldpc_code_query", "ldpc_code_tune", "ldpc_decode",
     "ldpc_batch_create", "ldpc_batch_launch", "ldpc_batch_query", "ldpc_batch_destroy",
     "ldpc_decode_batched", "Problem", "Batch", "BatchOptions", "decode_batched", "new_outputs",
     "ldpc_last_error", "decode", "LdpcError", "msg_flag",
-    "LDPC_FLAG_EARLY_STOP", "LDPC_FLAG_MSG_FP16", "LDPC_FLAG_MSG_BF16",
+    "LDPC_FLAG_EARLY_STOP", "LDPC_FLAG_MSG_FP16", "LDPC_FLAG_MSG_BF16", "LDPC_FLAG_OUT_PACKED",
 ]
 
 
@@ -122,9 +123,10 @@ class Code:
 
 def decode(code: Code, llr: torch.Tensor, max_iter: int, *, early_stop: bool = True,
            msg: str = "fp32", want_post: bool = True, want_syn: bool = True, out=None,
-           stream=None):
+           stream=None, packed: bool = False):
     """Decode a (F, n) float32 device tensor; returns dict of device tensors
-    hard (uint8), post (float32, optional), iters (int32), syn_ok (uint8)."""
+    hard (uint8, (F, n), or (F, ceil(n/8)) bit-packed LSB first with
+    ``packed``), post (float32, optional), iters (int32), syn_ok (uint8)."""
     if llr.dtype != torch.float32 or llr.dim() != 2 or llr.shape[1] != code.n:
         raise ValueError("llr must be a (F, n) float32 tensor")
     if not llr.is_cuda or not llr.is_contiguous():
@@ -132,11 +134,9 @@ def decode(code: Code, llr: torch.Tensor, max_iter: int, *, early_stop: bool = T
     F = llr.shape[0]
     dev = llr.device
     if out is None:
-        out = dict(hard=torch.empty((F, code.n), dtype=torch.uint8, device=dev),
-                   post=torch.empty((F, code.n), dtype=torch.float32, device=dev) if want_post else None,
-                   iters=torch.empty((F,), dtype=torch.int32, device=dev),
-                   syn_ok=torch.empty((F,), dtype=torch.uint8, device=dev) if want_syn else None)
-    flags = msg_flag(msg) | (LDPC_FLAG_EARLY_STOP if early_stop else 0)
+        out = new_outputs(F, code.n, dev, want_post, want_syn, packed)
+    _check_outputs(out, F, code.n, packed)
+    flags = msg_flag(msg) | (LDPC_FLAG_EARLY_STOP if early_stop else 0) | (LDPC_FLAG_OUT_PACKED if packed else 0)
     s = stream if stream is not None else torch.cuda.current_stream(dev)
     ldpc_decode(code.handle, llr.data_ptr(), F, max_iter, flags, out["hard"].data_ptr(),
                 out["post"].data_ptr() if out.get("post") is not None else 0,
@@ -175,8 +175,23 @@ class BatchOptions:
         return _native.ldpc_batch_options(*self.as_tuple())
 
 
-def new_outputs(F: int, n: int, device, want_post=True, want_syn=True) -> dict:
-    return dict(hard=torch.empty((F, n), dtype=torch.uint8, device=device),
+def hard_width(n: int, packed: bool) -> int:
+    return (n + 7) // 8 if packed else n
+
+
+def _check_outputs(out, F, n, packed):
+    if tuple(out["hard"].shape) != (F, hard_width(n, packed)) or out["hard"].dtype != torch.uint8:
+        raise ValueError("hard must be a (F, %d) uint8 tensor" % hard_width(n, packed))
+    if tuple(out["iters"].shape) != (F,) or out["iters"].dtype != torch.int32:
+        raise ValueError("iters must be a (F,) int32 tensor")
+    if out.get("post") is not None and (tuple(out["post"].shape) != (F, n) or out["post"].dtype != torch.float32):
+        raise ValueError("post must be a (F, n) float32 tensor")
+    if out.get("syn_ok") is not None and (tuple(out["syn_ok"].shape) != (F,) or out["syn_ok"].dtype != torch.uint8):
+        raise ValueError("syn_ok must be a (F,) uint8 tensor")
+
+
+def new_outputs(F: int, n: int, device, want_post=True, want_syn=True, packed=False) -> dict:
+    return dict(hard=torch.empty((F, hard_width(n, packed)), dtype=torch.uint8, device=device),
                 post=torch.empty((F, n), dtype=torch.float32, device=device) if want_post else None,
                 iters=torch.empty((F,), dtype=torch.int32, device=device),
                 syn_ok=torch.empty((F,), dtype=torch.uint8, device=device) if want_syn else None)
@@ -188,13 +203,15 @@ class Problem:
     unless given)."""
 
     def __init__(self, code: Code, llr: torch.Tensor, max_iter: int, *, out=None, want_post=True,
-                 want_syn=True):
+                 want_syn=True, packed=False):
         if llr.dtype != torch.float32 or llr.dim() != 2 or llr.shape[1] != code.n:
             raise ValueError("llr must be a (F, n) float32 tensor")
         if not llr.is_cuda or not llr.is_contiguous():
             raise ValueError("llr must be a contiguous device tensor")
-        self.code, self.llr, self.max_iter = code, llr, int(max_iter)
-        self.out = out if out is not None else new_outputs(llr.shape[0], code.n, llr.device, want_post, want_syn)
+        self.code, self.llr, self.max_iter, self.packed = code, llr, int(max_iter), bool(packed)
+        self.out = out if out is not None else new_outputs(llr.shape[0], code.n, llr.device, want_post, want_syn,
+                                                           packed)
+        _check_outputs(self.out, llr.shape[0], code.n, packed)
 
     def _c(self):
         o = self.out
@@ -203,6 +220,14 @@ class Problem:
                                     o["post"].data_ptr() if o.get("post") is not None else None,
                                     o["iters"].data_ptr(),
                                     o["syn_ok"].data_ptr() if o.get("syn_ok") is not None else None)
+
+
+def _batch_flags(problems, msg, early_stop):
+    packed = {p.packed for p in problems}
+    if len(packed) > 1:
+        raise ValueError("all problems of a batch must use the same hard-decision layout")
+    return (msg_flag(msg) | (LDPC_FLAG_EARLY_STOP if early_stop else 0)
+            | (LDPC_FLAG_OUT_PACKED if packed == {True} else 0))
 
 
 def _problem_array(problems):
@@ -249,7 +274,7 @@ class Batch:
 
     def __init__(self, problems, *, msg="fp16", early_stop=True, options: BatchOptions | None = None):
         self.problems = list(problems)
-        self.flags = msg_flag(msg) | (LDPC_FLAG_EARLY_STOP if early_stop else 0)
+        self.flags = _batch_flags(self.problems, msg, early_stop)
         self.handle = ldpc_batch_create(self.problems, self.flags, options)
         self.info = ldpc_batch_query(self.handle)
 
@@ -273,7 +298,7 @@ class Batch:
 def decode_batched(problems, *, msg="fp16", early_stop=True, stream=None):
     """One-shot batched decode (ldpc_decode_batched), asynchronous on
     ``stream``; returns the problems' output dicts."""
-    flags = msg_flag(msg) | (LDPC_FLAG_EARLY_STOP if early_stop else 0)
+    flags = _batch_flags(problems, msg, early_stop)
     dev = problems[0].llr.device if problems else torch.device("cuda", 0)
     s = stream if stream is not None else torch.cuda.current_stream(dev)
     ldpc_decode_batched(problems, flags, s.cuda_stream)

@@ -22,6 +22,7 @@ LDPC_GROUPS_EXPLICIT = 1
 LDPC_FLAG_EARLY_STOP = 0x1
 LDPC_FLAG_MSG_FP16 = 0x2
 LDPC_FLAG_MSG_BF16 = 0x4
+LDPC_FLAG_OUT_PACKED = 0x8
 
 EXPORTS = ("ldpc_code_create", "ldpc_code_destroy", "ldpc_code_query", "ldpc_code_tune",
            "ldpc_decode", "ldpc_batch_create", "ldpc_batch_launch", "ldpc_batch_query",

@@ -181,7 +181,7 @@ MsgKind msg_kind(uint32_t flags) {
 }
 
 int check_flags(uint32_t flags) {
-    const uint32_t known = LDPC_FLAG_EARLY_STOP | LDPC_FLAG_MSG_FP16 | LDPC_FLAG_MSG_BF16;
+    const uint32_t known = LDPC_FLAG_EARLY_STOP | LDPC_FLAG_MSG_FP16 | LDPC_FLAG_MSG_BF16 | LDPC_FLAG_OUT_PACKED;
     if (flags & ~known) return fail(LDPC_EINVAL, "unknown flag bits");
     if ((flags & LDPC_FLAG_MSG_FP16) && (flags & LDPC_FLAG_MSG_BF16))
         return fail(LDPC_EINVAL, "MSG_FP16 and MSG_BF16 are exclusive");
@@ -234,6 +234,7 @@ Problem make_problem(const ldpc_code* c, const Layout& lay, const float* llr, in
 
 void set_launch_constants(DecodeArgs& a, uint32_t flags, size_t lds) {
     a.early_stop = (flags & LDPC_FLAG_EARLY_STOP) ? 1 : 0;
+    a.packed = (flags & LDPC_FLAG_OUT_PACKED) ? 1 : 0;
     a.sh_offset = (int32_t)(lds - 16);
     a.ymin = (float)(kXMin * kLog2e);
     a.ymax = (float)(kXMax * kLog2e);

@@ -107,6 +107,7 @@ struct DecodeArgs {
     int32_t total_frames;
     uint32_t* work;       // this launch's {next frame, finished workgroups}, zero at launch
     int32_t early_stop;
+    int32_t packed;       // hard decisions packed 8 per byte (LSB first)
     int32_t sh_offset;    // byte offset of the workgroup state (frame, flags, problem)
     float ymin, ymax;     // clamp of |VN->CN message|, log2 units
     float cmin;           // lower clamp of the complement 1 - prod tanh

@@ -257,13 +257,31 @@ __device__ __forceinline__ void init_frame(const Problem& p, int frame, int tid,
     for (int q = tid; q < words; q += nt) lds_i32((uint32_t)p.l_offset + 4u * q) = 0;
 }
 
-__device__ __forceinline__ void write_outputs(const Problem& p, int frame, int used, int fail, int tid, int nt) {
-    uint8_t* hd = p.hard + (size_t)frame * p.n;
+__device__ __forceinline__ void write_outputs(const DecodeArgs& a, const Problem& p, int frame, int used, int fail,
+                                              int tid, int nt) {
     float* po = p.post ? p.post + (size_t)frame * p.n : nullptr;
-    for (int v = tid; v < p.n; v += nt) {
-        const float x = lds_f32(4u * v);
-        hd[v] = x < 0.0f ? 1 : 0;
-        if (po) po[v] = x * kLn2F;
+    if (a.packed) {
+        // byte q holds d_{8q} .. d_{8q+7}, bit k = d_{8q+k}; bits past n are 0
+        const int nb = (p.n + 7) >> 3;
+        uint8_t* hd = p.hard + (size_t)frame * nb;
+        for (int q = tid; q < nb; q += nt) {
+            uint32_t bits = 0;
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                const int v = 8 * q + k;
+                if (v < p.n) bits |= (lds_f32(4u * v) < 0.0f ? 1u : 0u) << k;
+            }
+            hd[q] = (uint8_t)bits;
+        }
+        if (po)
+            for (int v = tid; v < p.n; v += nt) po[v] = lds_f32(4u * v) * kLn2F;
+    } else {
+        uint8_t* hd = p.hard + (size_t)frame * p.n;
+        for (int v = tid; v < p.n; v += nt) {
+            const float x = lds_f32(4u * v);
+            hd[v] = x < 0.0f ? 1 : 0;
+            if (po) po[v] = x * kLn2F;
+        }
     }
     if (tid == 0) {
         p.iters[frame] = used;
@@ -363,7 +381,7 @@ __global__ __launch_bounds__(MaxThreads<D>::value) void ndgsbp_kernel(DecodeArgs
         const int fail = lds_i32(fl);
         if (!((a.early_stop && !fail) || used == p.max_iter)) continue;
         // finished: outputs, then the next frame (of this or another problem)
-        write_outputs(p, frame, used, fail, tid, nt);
+        write_outputs(a, p, frame, used, fail, tid, nt);
         if (tid == 0) claim_frame(a, sh);
         __syncthreads();
         frame = __builtin_amdgcn_readfirstlane(lds_i32(sh));

@@ -231,3 +231,28 @@ def test_async_batched_calls_in_flight(mixed):
             got = _host(p.out)
             for k in want[i]:
                 assert np.array_equal(got[k], want[i][k]), (idx, i, k)
+
+
+def test_packed_hard_decisions(mixed):
+    """LDPC_FLAG_OUT_PACKED: byte q bit k = d_{8q+k}, bits past n zero; the
+    same decisions as the byte-per-bit layout, single and batched."""
+    for i in (0, 1, 6):
+        p = mixed.specs[i]
+        ref = _single(mixed, i, "fp16")
+        got = nd.decode(mixed.codes[i], mixed.dllr[i], p["max_iter"], msg="fp16", packed=True)
+        torch.cuda.synchronize()
+        hb = got["hard"].cpu().numpy()
+        n = mixed.codes[i].n
+        assert hb.shape == (p["frames"], (n + 7) // 8)
+        assert np.array_equal(np.unpackbits(hb, axis=1, bitorder="little")[:, :n], ref["hard"])
+        assert not np.any(np.unpackbits(hb, axis=1, bitorder="little")[:, n:])
+        for k in ("post", "iters", "syn_ok"):
+            assert np.array_equal(got[k].cpu().numpy(), ref[k])
+    probs = [nd.Problem(c, x, p["max_iter"], packed=True) for c, x, p in zip(mixed.codes, mixed.dllr, mixed.specs)]
+    nd.decode_batched(probs, msg="fp16")
+    torch.cuda.synchronize()
+    for i, pr in enumerate(probs):
+        n = mixed.codes[i].n
+        ref = _single(mixed, i, "fp16")
+        hb = pr.out["hard"].cpu().numpy()
+        assert np.array_equal(np.unpackbits(hb, axis=1, bitorder="little")[:, :n], ref["hard"]), i
