@@ -42,6 +42,7 @@ extern "C" {
 #define LDPC_FLAG_MSG_FP16 0x2u   /* store CN->VN messages as IEEE binary16           */
 #define LDPC_FLAG_MSG_BF16 0x4u   /* store CN->VN messages as bfloat16                */
 #define LDPC_FLAG_OUT_PACKED 0x8u /* hard decisions 8 per byte: see ldpc_decode        */
+#define LDPC_FLAG_TIER_HBM 0x10u  /* ldpc_decode: HBM tier even if the code fits LDS    */
 
 typedef struct ldpc_code* ldpc_code_t;
 
@@ -84,6 +85,8 @@ typedef struct {
     int32_t device;
     int64_t lds_bytes_fp32;  /* per-frame LDS of the FP32-message kernel      */
     int64_t lds_bytes_16;    /* per-frame LDS of the FP16-message kernel      */
+    int64_t lds_limit;       /* LDS per workgroup on the device; codes above
+                                it decode in the HBM tier                     */
     int32_t lanes_fp32;      /* lanes per CN visit used with FP32 messages    */
     int32_t lanes_fp16;      /* ... with FP16 messages                        */
     int32_t lanes_bf16;      /* ... with BF16 messages                        */
@@ -127,8 +130,17 @@ int ldpc_code_tune(ldpc_code_t code, uint32_t msg_flags, int32_t lanes_per_cn);
  * messages as they stood before the group. With LDPC_FLAG_EARLY_STOP a frame
  * stops after the first iteration whose syndrome is zero; otherwise every
  * frame runs max_iter iterations. At most one of MSG_FP16 / MSG_BF16.
+ * Tiers: a frame's posteriors and messages stay in LDS for its whole decode
+ * when they fit (lds_bytes_* <= lds_limit); otherwise (or with
+ * LDPC_FLAG_TIER_HBM) they live in a frame-interleaved workspace in device
+ * memory that the code allocates on first use and grows when a larger launch
+ * needs it (the one case in which ldpc_decode allocates); HBM-tier decodes
+ * of one code run one after another on the device (each waits for the
+ * previous one). Both tiers compute the same values: the HBM tier equals the
+ * LDS tier with one lane per CN visit, bit for bit.
  * Errors: EINVAL (NULL code/llr/hard/iters, num_frames < 0, max_iter < 1,
- * bad flags), EUNSUPPORTED (no kernel variant fits the code), EHIP. */
+ * bad flags), EUNSUPPORTED (no kernel variant fits the code), ENOMEM (HBM
+ * workspace), EHIP. */
 int ldpc_decode(ldpc_code_t code, const float* llr, int32_t num_frames, int32_t max_iter,
                 uint32_t flags, uint8_t* hard, float* post, int32_t* iters, uint8_t* syn_ok,
                 void* hip_stream);

@@ -23,6 +23,7 @@ LDPC_FLAG_EARLY_STOP = 0x1
 LDPC_FLAG_MSG_FP16 = 0x2
 LDPC_FLAG_MSG_BF16 = 0x4
 LDPC_FLAG_OUT_PACKED = 0x8
+LDPC_FLAG_TIER_HBM = 0x10
 
 EXPORTS = ("ldpc_code_create", "ldpc_code_destroy", "ldpc_code_query", "ldpc_code_tune",
            "ldpc_decode", "ldpc_batch_create", "ldpc_batch_launch", "ldpc_batch_query",
@@ -48,7 +49,7 @@ class ldpc_code_info(ctypes.Structure):
                 ("edge_updates", ctypes.c_int64), ("max_cn_degree", ctypes.c_int32),
                 ("max_vn_degree", ctypes.c_int32), ("device", ctypes.c_int32),
                 ("lds_bytes_fp32", ctypes.c_int64), ("lds_bytes_16", ctypes.c_int64),
-                ("lanes_fp32", ctypes.c_int32), ("lanes_fp16", ctypes.c_int32),
+                ("lds_limit", ctypes.c_int64), ("lanes_fp32", ctypes.c_int32), ("lanes_fp16", ctypes.c_int32),
                 ("lanes_bf16", ctypes.c_int32)]
 
 

@@ -1,0 +1,341 @@
+// gfx950 kernel of the NDGSBP decoder for codes whose per-frame state does
+// not fit in LDS: frame-interleaved state in HBM (Sec. II-C, Steps 2-4).
+//
+// A workgroup owns a tile of 64 frame slots, slot l = lane l of every wave.
+// Its posteriors, delta slots and CN->VN messages live in a device workspace
+// laid out row-major with the 64 slots fastest: float row r (posterior r,
+// or delta slot r - ds_start) at fws[r * 64 + l]; message k of CN c at
+// mws[(c * D + k) * 64 + l]. A wave processes one CN visit at a time for all
+// 64 frames: the visit's edge table is the same for every lane, so it comes
+// through scalar loads, and every access to the frame state is one 256-byte
+// (FP32) or 128-byte (16-bit) row per instruction, fully coalesced.
+//
+// Per iteration, for each group g in order: the waves split the group's
+// visits (eq. (1) and the add-back, the same arithmetic as the LDS kernel,
+// cn_core with one lane per CN row); barrier; fix-up of VNs with several
+// edges in the group; barrier. After the last group: per-slot syndrome
+// (Step 4); slots whose frame is finished write its outputs, and once enough
+// slots are idle they take new frames from the launch's work counter, so the
+// tile keeps decoding while frames need different numbers of iterations.
+//
+// Messages are not cleared when a frame starts: in a frame's first
+// iteration, the first visit of each CN uses 0 as the old message (the
+// initial value), and every later visit reads what an earlier visit of the
+// same iteration wrote (each visit writes all D messages of its CN).
+#include <hip/hip_runtime.h>
+
+#include "ndgsbp_cn.h"
+#include "ndgsbp_hbm.h"
+#include "ndgsbp_internal.h"
+#include "ndgsbp_math.h"
+
+namespace ndgsbp {
+namespace {
+
+using namespace dev;
+
+constexpr int kSlots = 64;       // frames per workgroup tile (one per lane)
+constexpr int kMaxWaves = 16;
+
+typedef const __attribute__((address_space(4))) uint32_t const_u32;
+__device__ __forceinline__ uint32_t tbl_u32(const uint32_t* base, uint32_t i) { return ((const_u32*)base)[i]; }
+__device__ __forceinline__ int32_t tbl_i32(const int32_t* base, uint32_t i) {
+    return (int32_t)((const_u32*)base)[i];
+}
+
+// Workgroup-size cap per degree: a lane holds a whole CN row in registers.
+template <int D>
+struct HbmMaxThreads {
+    static constexpr int value = D >= 24 ? 256 : D >= 12 ? 512 : 1024;
+};
+
+// Wave 0: takes frames from the launch's work counter for the slots in
+// `want` (a lane mask), in lane order; lane l gets *frame (-1 if the launch
+// has none left). Returns the slots that got a frame; clears *more once the
+// counter has passed the last frame.
+__device__ __forceinline__ uint64_t claim_slots(const HbmArgs& a, uint64_t want, int lane, int* frame, int* more) {
+    const int cnt = __popcll(want);
+    if (cnt == 0) return 0;
+    unsigned base = 0;
+    if (lane == 0) base = atomicAdd(a.work, (unsigned)cnt);
+    base = __shfl(base, 0);
+    const bool mine = (want >> lane) & 1ull;
+    const unsigned f = base + (unsigned)__popcll(want & ((1ull << lane) - 1ull));
+    const bool got = mine && f < (unsigned)a.p.num_frames;
+    *frame = got ? (int)f : -1;
+    if (lane == 0 && base + (unsigned)cnt >= (unsigned)a.p.num_frames) *more = 0;
+    return __ballot(got);
+}
+
+template <class M, int D, bool UNI>
+__global__ __launch_bounds__(HbmMaxThreads<D>::value) void ndgsbp_hbm_kernel(HbmArgs a) {
+    using T = typename M::T;
+    constexpr int SD = (D + 3) / 4 * 4;
+    constexpr int W = (2 * D + 3) / 4 * 4;  // words per visit record (one lane per CN)
+    const Problem& p = a.p;
+    const int tid = threadIdx.x, nt = blockDim.x;
+    const int lane = tid & 63, wv = tid >> 6, nw = nt >> 6;
+    float* fw = a.fws + (size_t)blockIdx.x * a.fws_tile;
+    T* mw = reinterpret_cast<T*>(a.mws) + (size_t)blockIdx.x * a.mws_tile;
+
+    __shared__ int s_frame[kSlots];   // frame of each slot, -1: none
+    __shared__ int s_next[kSlots];    // frame a slot takes after its outputs are written
+    __shared__ int s_used[kSlots];    // iterations run on it
+    __shared__ int s_fail[kMaxWaves][kSlots];
+    __shared__ unsigned long long s_mask[3];  // [0] active, [1] to retire, [2] just filled
+    __shared__ int s_check;           // some slot checks its syndrome this iteration
+    __shared__ int s_more;            // the launch may still have frames
+
+    if (wv == 0) {
+        if (lane == 0) s_more = 1;
+        int f = -1;
+        const uint64_t got = claim_slots(a, ~0ull, lane, &f, &s_more);
+        s_frame[lane] = f;
+        s_used[lane] = 0;
+        if (lane == 0) {
+            s_mask[0] = got;
+            s_mask[1] = 0;
+            s_mask[2] = got;
+        }
+    }
+    __syncthreads();
+
+    for (;;) {
+        // start the frames of newly filled slots: posteriors = channel LLRs
+        const uint64_t fill = s_mask[2];
+        if (fill) {
+            const bool mine = (fill >> lane) & 1ull;
+            const int f = s_frame[lane];
+            const float* y = p.llr + (size_t)(mine ? f : 0) * p.n;
+            for (int v = wv; v < p.n; v += nw)
+                if (mine) fw[(size_t)v * kSlots + lane] = y[v] * kLog2eF + 0.0f;  // -0.0 -> +0.0
+            // posterior n: scratch of padding edges; n + 1: 0, syndrome padding
+            if (mine && wv == 0) {
+                fw[(size_t)p.n * kSlots + lane] = 0.0f;
+                fw[(size_t)(p.n + 1) * kSlots + lane] = 0.0f;
+            }
+        }
+        __syncthreads();
+        const uint64_t active = s_mask[0];
+        if (active == 0) break;
+        const bool fresh = s_used[lane] == 0;  // this slot's frame is in its first iteration
+
+        for (int g = 0; g < p.G; ++g) {
+            const int j0 = tbl_i32(p.visit_ptr, g), j1 = tbl_i32(p.visit_ptr, g + 1);
+            for (int j = j0 + wv; j < j1; j += nw) {
+                const int cn = tbl_i32(p.vcn, j);
+                const bool zero_old = fresh && tbl_u32(a.vfirst, j);
+                float pv[D], lo[D], wvals[D];
+                bool real[D], direct[D];
+                T st[D];
+                uint32_t pa[D], ta[D];
+#pragma unroll
+                for (int k = 0; k < D; ++k) {
+                    pa[k] = tbl_u32(p.vw, (uint32_t)j * W + k);
+                    ta[k] = tbl_u32(p.vw, (uint32_t)j * W + D + k);
+                }
+                T* row = mw + (size_t)cn * D * kSlots + lane;
+#pragma unroll
+                for (int k = 0; k < D; ++k) {
+                    // byte offset 4r of float row r -> element r * 64
+                    pv[k] = fw[(size_t)pa[k] * (kSlots / 4) + lane];
+                    lo[k] = zero_old ? 0.0f : M::unpack(row[k * kSlots]);
+                    real[k] = pa[k] != p.pad_b;
+                    direct[k] = ta[k] < p.ds_start_b;
+                }
+                cn_core<M, D, UNI, 1>(pv, lo, real, direct, a.ymin, a.ymax, a.cmin, st, wvals);
+#pragma unroll
+                for (int k = 0; k < D; ++k) {
+                    fw[(size_t)ta[k] * (kSlots / 4) + lane] = wvals[k];
+                    row[k * kSlots] = st[k];
+                }
+            }
+            __syncthreads();
+            const int q0 = tbl_i32(p.fix_ptr, g), q1 = tbl_i32(p.fix_ptr, g + 1);
+            if (q1 > q0) {
+                for (int q = q0 + wv; q < q1; q += nw) {
+                    const uint32_t x = tbl_u32(reinterpret_cast<const uint32_t*>(p.fix), 2 * q);
+                    const uint32_t y = tbl_u32(reinterpret_cast<const uint32_t*>(p.fix), 2 * q + 1);
+                    const uint32_t v = x & 0xffffu, c = x >> 16;
+                    const size_t d0 = ((size_t)(p.ds_start_b >> 2) + y) * kSlots + lane;
+                    float acc = fw[(size_t)v * kSlots + lane];
+                    for (uint32_t k = 0; k < c; ++k) acc += fw[d0 + (size_t)k * kSlots];
+                    fw[(size_t)v * kSlots + lane] = acc;
+                }
+                __syncthreads();
+            }
+        }
+
+        // a4: which slots check their syndrome after this iteration
+        if (wv == 0) {
+            const bool act = (active >> lane) & 1ull;
+            const int used = s_used[lane] + (act ? 1 : 0);
+            s_used[lane] = used;
+            const bool chk = act && (a.early_stop || used == p.max_iter);
+            const uint64_t any = __ballot(chk);
+            if (lane == 0) s_check = any != 0;
+        }
+        __syncthreads();
+        if (s_check) {
+            // hard decision = sign bit of the posterior (no -0.0 is stored)
+            uint32_t x = 0;
+            for (int c = wv; c < p.m; c += nw) {
+                uint32_t par = 0;
+#pragma unroll
+                for (int k = 0; k < SD; ++k)
+                    par ^= __float_as_uint(fw[(size_t)tbl_u32(p.syn_col, (uint32_t)c * SD + k) * (kSlots / 4) + lane]);
+                x |= par;
+            }
+            s_fail[wv][lane] = (int)(x >> 31);
+        }
+        __syncthreads();
+
+        // retire finished frames, refill idle slots
+        if (wv == 0) {
+            const bool act = (active >> lane) & 1ull;
+            int fail = 0;
+            if (s_check)
+                for (int w = 0; w < nw; ++w) fail |= s_fail[w][lane];
+            const int used = s_used[lane];
+            const bool chk = act && (a.early_stop || used == p.max_iter);
+            const bool done = chk && ((a.early_stop && !fail) || used == p.max_iter);
+            if (done) {
+                const int f = s_frame[lane];
+                p.iters[f] = used;
+                if (p.syn_ok) p.syn_ok[f] = fail ? 0 : 1;
+            }
+            const uint64_t dmask = __ballot(done);
+            const uint64_t still = active & ~dmask;
+            const uint64_t idle = ~still;
+            uint64_t filled = 0;
+            int nf = -1;
+            // refill once a quarter of the tile is idle, or when it is empty;
+            // a retiring slot keeps its frame until its outputs are written
+            if (s_more && (__popcll(idle) >= kSlots / 4 || still == 0))
+                filled = claim_slots(a, idle, lane, &nf, &s_more);
+            s_next[lane] = nf;
+            if (lane == 0) {
+                s_mask[1] = dmask;
+                s_mask[2] = filled;
+                s_mask[0] = still | filled;
+            }
+        }
+        __syncthreads();
+        // outputs of the retired frames, one frame at a time, all lanes
+        uint64_t ret = s_mask[1];
+        while (ret) {
+            const int sl = __ffsll((long long)ret) - 1;
+            ret &= ret - 1;
+            const int f = s_frame[sl];
+            const float* col = fw + sl;
+            float* po = p.post ? p.post + (size_t)f * p.n : nullptr;
+            if (a.packed) {
+                const int nb = (p.n + 7) >> 3;
+                uint8_t* hd = p.hard + (size_t)f * nb;
+                for (int q = tid; q < nb; q += nt) {
+                    uint32_t bits = 0;
+#pragma unroll
+                    for (int k = 0; k < 8; ++k) {
+                        const int v = 8 * q + k;
+                        if (v < p.n) bits |= (col[(size_t)v * kSlots] < 0.0f ? 1u : 0u) << k;
+                    }
+                    hd[q] = (uint8_t)bits;
+                }
+                if (po)
+                    for (int v = tid; v < p.n; v += nt) po[v] = col[(size_t)v * kSlots] * kLn2F;
+            } else {
+                uint8_t* hd = p.hard + (size_t)f * p.n;
+                for (int v = tid; v < p.n; v += nt) {
+                    const float x = col[(size_t)v * kSlots];
+                    hd[v] = x < 0.0f ? 1 : 0;
+                    if (po) po[v] = x * kLn2F;
+                }
+            }
+        }
+        __syncthreads();
+        if (wv == 0) {
+            const bool mine = (s_mask[2] >> lane) & 1ull;
+            const bool retired = (s_mask[1] >> lane) & 1ull;
+            if (mine) {
+                s_frame[lane] = s_next[lane];
+                s_used[lane] = 0;
+            } else if (retired) {
+                s_frame[lane] = -1;
+            }
+        }
+        __syncthreads();
+    }
+
+    // the last workgroup out resets the launch's counters for the next launch
+    __threadfence();
+    if (tid == 0) {
+        const unsigned done_wgs = atomicAdd(a.work + 1, 1u);
+        if (done_wgs == gridDim.x - 1) {
+            atomicExch(a.work, 0u);
+            atomicExch(a.work + 1, 0u);
+        }
+    }
+}
+
+template <class M, int D, bool UNI>
+hipError_t run_hbm(const HbmArgs& a, int blocks, int threads, hipStream_t s) {
+    const void* fn = reinterpret_cast<const void*>(&ndgsbp_hbm_kernel<M, D, UNI>);
+    HbmArgs copy = a;
+    void* args[] = {&copy};
+    return hipLaunchKernel(fn, dim3(blocks), dim3(threads), args, 0, s);
+}
+
+template <class M, int D, bool UNI>
+hipError_t occ_hbm(int threads, int* out) {
+    const void* fn = reinterpret_cast<const void*>(&ndgsbp_hbm_kernel<M, D, UNI>);
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(out, fn, threads, 0);
+}
+
+template <class M, int D>
+hipError_t hbm_by_uniform(bool uni, bool launch, const HbmArgs* a, int blocks, int threads, hipStream_t s,
+                          int* out) {
+    if (launch) return uni ? run_hbm<M, D, true>(*a, blocks, threads, s) : run_hbm<M, D, false>(*a, blocks, threads, s);
+    return uni ? occ_hbm<M, D, true>(threads, out) : occ_hbm<M, D, false>(threads, out);
+}
+
+template <class M>
+hipError_t hbm_by_degree(int D, bool uni, bool launch, const HbmArgs* a, int blocks, int threads, hipStream_t s,
+                         int* out) {
+    switch (D) {
+        case 4: return hbm_by_uniform<M, 4>(uni, launch, a, blocks, threads, s, out);
+        case 6: return hbm_by_uniform<M, 6>(uni, launch, a, blocks, threads, s, out);
+        case 7: return hbm_by_uniform<M, 7>(uni, launch, a, blocks, threads, s, out);
+        case 8: return hbm_by_uniform<M, 8>(uni, launch, a, blocks, threads, s, out);
+        case 12: return hbm_by_uniform<M, 12>(uni, launch, a, blocks, threads, s, out);
+        case 16: return hbm_by_uniform<M, 16>(uni, launch, a, blocks, threads, s, out);
+        case 24: return hbm_by_uniform<M, 24>(uni, launch, a, blocks, threads, s, out);
+        case 32: return hbm_by_uniform<M, 32>(uni, launch, a, blocks, threads, s, out);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t hbm_dispatch(MsgKind kind, int D, bool uni, bool launch, const HbmArgs* a, int blocks, int threads,
+                        hipStream_t s, int* out) {
+    switch (kind) {
+        case kMsgF32: return hbm_by_degree<MsgF32>(D, uni, launch, a, blocks, threads, s, out);
+        case kMsgF16: return hbm_by_degree<MsgF16>(D, uni, launch, a, blocks, threads, s, out);
+        case kMsgBF16: return hbm_by_degree<MsgBF16>(D, uni, launch, a, blocks, threads, s, out);
+    }
+    return hipErrorInvalidValue;
+}
+
+}  // namespace
+
+int hbm_max_threads(int D) { return D >= 24 ? 256 : D >= 12 ? 512 : 1024; }
+int hbm_slots() { return kSlots; }
+
+hipError_t launch_hbm(const HbmArgs& a, MsgKind kind, int D, bool uniform, int blocks, int threads,
+                      hipStream_t stream) {
+    return hbm_dispatch(kind, D, uniform, true, &a, blocks, threads, stream, nullptr);
+}
+
+hipError_t hbm_occupancy(MsgKind kind, int D, bool uniform, int threads, int* blocks_per_cu) {
+    return hbm_dispatch(kind, D, uniform, false, nullptr, 0, threads, nullptr, blocks_per_cu);
+}
+
+}  // namespace ndgsbp

@@ -13,6 +13,8 @@
 #include <vector>
 
 #include "ndgsbp.h"
+#include "ndgsbp_code.h"
+#include "ndgsbp_hbm.h"
 #include "ndgsbp_internal.h"
 
 using namespace ndgsbp;
@@ -59,6 +61,12 @@ hipError_t upload(T** dst, const std::vector<T>& src) {
 void free_tables(ldpc_code* c) {
     DeviceTables& t = c->dev;
     (void)hipFree(t.vcn);
+    (void)hipFree(t.vfirst);
+    (void)hipFree(c->hbm_ws);
+    c->hbm_ws = nullptr;
+    c->hbm_ws_bytes = 0;
+    if (c->hbm_last) (void)hipEventDestroy(c->hbm_last);
+    c->hbm_last = nullptr;
     (void)hipFree(t.visit_ptr);
     (void)hipFree(t.fix);
     (void)hipFree(t.fix_ptr);
@@ -181,7 +189,8 @@ MsgKind msg_kind(uint32_t flags) {
 }
 
 int check_flags(uint32_t flags) {
-    const uint32_t known = LDPC_FLAG_EARLY_STOP | LDPC_FLAG_MSG_FP16 | LDPC_FLAG_MSG_BF16 | LDPC_FLAG_OUT_PACKED;
+    const uint32_t known =
+        LDPC_FLAG_EARLY_STOP | LDPC_FLAG_MSG_FP16 | LDPC_FLAG_MSG_BF16 | LDPC_FLAG_OUT_PACKED | LDPC_FLAG_TIER_HBM;
     if (flags & ~known) return fail(LDPC_EINVAL, "unknown flag bits");
     if ((flags & LDPC_FLAG_MSG_FP16) && (flags & LDPC_FLAG_MSG_BF16))
         return fail(LDPC_EINVAL, "MSG_FP16 and MSG_BF16 are exclusive");
@@ -357,7 +366,7 @@ int form_classes(const ldpc_problem* probs, int32_t count, MsgKind kind, const l
         const Layout& lay = q.code->lay[h - 1];
         if (!lay.valid) return fail(LDPC_EUNSUPPORTED, at + "no kernel variant with that mapping");
         int rc = check_lds(q.code, lay, kind);
-        if (rc) return fail(rc, at + g_last_error);
+        if (rc) return fail(rc, at + g_last_error + " (batches run the LDS tier; ldpc_decode takes the HBM tier)");
         Item it;
         it.idx = i;
         it.lay = &lay;
@@ -502,6 +511,73 @@ hipError_t get_stage(int device, DeviceStage** out) {
     g_stage[device] = ds;
     *out = ds;
     return hipSuccess;
+}
+
+// HBM tier (codes beyond LDS, or LDPC_FLAG_TIER_HBM): one-lane tables,
+// 64-frame tiles in a workspace the code keeps and grows on demand.
+int decode_hbm(ldpc_code* c, const float* llr, int32_t num_frames, int32_t max_iter, uint32_t flags, uint8_t* hard,
+               float* post, int32_t* iters, uint8_t* syn_ok, hipStream_t stream) {
+    const MsgKind kind = msg_kind(flags);
+    const Layout& lay = c->lay[0];
+    if (!lay.valid) return fail(LDPC_EUNSUPPORTED, "no one-lane tables for the HBM tier");
+    const int slots = hbm_slots();
+    const int waves = std::max(1, std::min(hbm_max_threads(lay.D) / 64, c->max_group_visits));
+    const int threads = 64 * waves;
+    int per_cu = 0;
+    hipError_t e = hbm_occupancy(kind, lay.D, lay.uniform, threads, &per_cu);
+    if (e != hipSuccess) return hip_fail(e, "occupancy query (HBM tier)");
+    if (per_cu < 1) return fail(LDPC_EUNSUPPORTED, "HBM-tier kernel cannot be resident");
+    const int64_t tiles_needed = (num_frames + slots - 1) / slots;
+    const int blocks = (int)std::min<int64_t>((int64_t)per_cu * c->num_cus, tiles_needed);
+    const uint64_t frows = (uint64_t)c->ds_start + (uint64_t)c->max_slots;
+    const uint64_t fws_tile = frows * slots;
+    const uint64_t mws_tile = (uint64_t)c->m * lay.D * slots;
+    const size_t msg_size = kind == kMsgF32 ? 4 : 2;
+    const size_t ftile_bytes = (fws_tile * 4 + 255) & ~(size_t)255;
+    const size_t need = (size_t)blocks * ftile_bytes + (size_t)blocks * mws_tile * msg_size;
+
+    std::lock_guard<std::mutex> lock(c->hbm_mu);
+    if (!c->hbm_last) {
+        e = hipEventCreateWithFlags(&c->hbm_last, hipEventDisableTiming);
+        if (e != hipSuccess) return hip_fail(e, "HBM-tier event");
+    }
+    if (need > c->hbm_ws_bytes) {
+        // no earlier HBM-tier launch of this code may still use the old one
+        if (c->hbm_used) {
+            e = hipEventSynchronize(c->hbm_last);
+            if (e != hipSuccess) return hip_fail(e, "HBM-tier workspace wait");
+        }
+        (void)hipFree(c->hbm_ws);
+        c->hbm_ws = nullptr;
+        c->hbm_ws_bytes = 0;
+        e = hipMalloc(&c->hbm_ws, need);
+        if (e != hipSuccess)
+            return e == hipErrorOutOfMemory ? fail(LDPC_ENOMEM, "HBM-tier workspace of " + std::to_string(need) + " B")
+                                            : hip_fail(e, "HBM-tier workspace");
+        c->hbm_ws_bytes = need;
+    }
+    HbmArgs a{};
+    a.p = make_problem(c, lay, llr, num_frames, max_iter, hard, post, iters, syn_ok);
+    a.vfirst = c->dev.vfirst;
+    a.fws = reinterpret_cast<float*>(c->hbm_ws);
+    a.mws = reinterpret_cast<unsigned char*>(c->hbm_ws) + (size_t)blocks * ftile_bytes;
+    a.fws_tile = ftile_bytes / 4;
+    a.mws_tile = mws_tile;
+    a.work = c->dev.work + 2 * (c->next_work.fetch_add(1) % kWorkRing);
+    a.early_stop = (flags & LDPC_FLAG_EARLY_STOP) ? 1 : 0;
+    a.packed = (flags & LDPC_FLAG_OUT_PACKED) ? 1 : 0;
+    a.ymin = (float)(kXMin * kLog2e);
+    a.ymax = (float)(kXMax * kLog2e);
+    a.cmin = (float)kXMin;
+    if (c->hbm_used) {
+        e = hipStreamWaitEvent(stream, c->hbm_last, 0);
+        if (e != hipSuccess) return hip_fail(e, "HBM-tier ordering");
+    }
+    e = launch_hbm(a, kind, lay.D, lay.uniform, blocks, threads, stream);
+    if (e == hipSuccess) e = hipEventRecord(c->hbm_last, stream);
+    if (e != hipSuccess) return hip_fail(e, "HBM-tier decode launch");
+    c->hbm_used = true;
+    return LDPC_OK;
 }
 
 // Grows a slot's tables to hold `n` problems (allocates only on growth).
@@ -681,7 +757,18 @@ int ldpc_code_create(const ldpc_h_csr* H, const ldpc_grouping* grouping, int32_t
         return fail(LDPC_EHIP, "cannot select device " + std::to_string(device));
     }
     hipError_t e = hipSuccess;
+    // first visit of each CN within an iteration (the HBM tier treats its
+    // old message as the initial 0 in a frame's first iteration)
+    std::vector<uint32_t> vfirst(vcn.size(), 0u);
+    {
+        std::vector<char> seen(m, 0);
+        for (size_t j = 0; j < vcn.size(); ++j) {
+            vfirst[j] = seen[vcn[j]] ? 0u : 1u;
+            seen[vcn[j]] = 1;
+        }
+    }
     if (e == hipSuccess) e = upload(&c->dev.vcn, vcn);
+    if (e == hipSuccess) e = upload(&c->dev.vfirst, vfirst);
     if (e == hipSuccess) e = upload(&c->dev.visit_ptr, visit_ptr);
     if (e == hipSuccess) e = upload(&c->dev.fix, fix);
     if (e == hipSuccess) e = upload(&c->dev.fix_ptr, fix_ptr);
@@ -733,6 +820,7 @@ int ldpc_code_query(ldpc_code_t c, ldpc_code_info* info) {
     info->device = c->device;
     info->lds_bytes_fp32 = (int64_t)lds_bytes(c, c->lay[c->lanes_for[kMsgF32] - 1], kMsgF32);
     info->lds_bytes_16 = (int64_t)lds_bytes(c, c->lay[c->lanes_for[kMsgF16] - 1], kMsgF16);
+    info->lds_limit = (int64_t)c->max_lds;
     info->lanes_fp32 = c->lanes_for[kMsgF32];
     info->lanes_fp16 = c->lanes_for[kMsgF16];
     info->lanes_bf16 = c->lanes_for[kMsgBF16];
@@ -771,8 +859,8 @@ int ldpc_decode(ldpc_code_t c, const float* llr, int32_t num_frames, int32_t max
 
     DeviceGuard guard(c->device);
     if (!guard.ok) return fail(LDPC_EHIP, "cannot select the code's device");
-    rc = check_lds(c, lay, kind);
-    if (rc) return rc;
+    if ((flags & LDPC_FLAG_TIER_HBM) || lds_bytes(c, lay, kind) > c->max_lds)
+        return decode_hbm(c, llr, num_frames, max_iter, flags, hard, post, iters, syn_ok, (hipStream_t)hip_stream);
     LaunchShape shape;
     shape.lanes = lay.H;
     shape.threads = threads_for(c, lay);
@@ -803,6 +891,7 @@ int ldpc_batch_create(const ldpc_problem* probs, int32_t count, uint32_t flags, 
     if (opt) o = *opt;
     rc = check_options(o);
     if (rc) return rc;
+    if (flags & LDPC_FLAG_TIER_HBM) return fail(LDPC_EUNSUPPORTED, "batches run the LDS tier only");
     const MsgKind kind = msg_kind(flags);
     ClassPlan plan;
     rc = form_classes(probs, count, kind, o, plan);
@@ -893,6 +982,7 @@ int ldpc_decode_batched(const ldpc_problem* probs, int32_t count, uint32_t flags
     g_last_error.clear();
     int rc = check_flags(flags);
     if (rc) return rc;
+    if (flags & LDPC_FLAG_TIER_HBM) return fail(LDPC_EUNSUPPORTED, "batches run the LDS tier only");
     const MsgKind kind = msg_kind(flags);
     const ldpc_batch_options o = default_batch_options();
     ClassPlan plan;

@@ -5,10 +5,6 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
-#include <atomic>
-#include <string>
-#include <vector>
-
 #include "ndgsbp.h"
 
 namespace ndgsbp {
@@ -54,24 +50,6 @@ constexpr double kXMin = 1.8715245937680347e-13;
 //     DH messages (FP32, or 16-bit with DH rounded up to even);
 //   at sh_offset (the last 16 bytes of the allocation, the same for every
 //     problem of a launch): int frame, int flag[2], int problem.
-
-struct DeviceTables {
-    int32_t* vcn = nullptr;
-    int32_t* visit_ptr = nullptr;  // G + 1
-    uint2* fix = nullptr;
-    int32_t* fix_ptr = nullptr;    // G + 1
-    uint32_t* work = nullptr;      // kWorkRing pairs {next frame, finished workgroups}
-};
-
-// The tables that depend on the CN-phase mapping (H lanes per CN visit).
-struct Layout {
-    bool valid = false;
-    int32_t H = 1;          // lanes per CN visit
-    int32_t D = 0;          // padded CN degree (kernel variant), a multiple of H
-    bool uniform = false;   // every CN has degree exactly D
-    uint32_t* vw = nullptr;       // edge half-records
-    uint32_t* syn_col = nullptr;  // m * SD
-};
 
 // One decode problem: a code's tables for one CN-lane mapping and the
 // buffers of one call.
@@ -138,24 +116,3 @@ constexpr int kMaxDegree = 32;
 constexpr int kWorkRing = 1024;
 
 }  // namespace ndgsbp
-
-struct ldpc_code {
-    int32_t device;
-    int32_t m, n;
-    int64_t nnz;
-    int32_t G;
-    int64_t cn_visits;
-    int64_t edge_updates;
-    int32_t max_cn_degree;
-    int32_t max_vn_degree;
-    int32_t max_group_visits;
-    int32_t max_slots;
-    ndgsbp::Layout lay[2];    // lay[H - 1]: tables for H lanes per CN visit
-    int32_t lanes_for[3];     // chosen H per message format (MsgKind)
-    int32_t lanes_default[3];
-    size_t max_lds;   // LDS a workgroup may use on the code's device
-    int32_t num_cus;  // compute units of the code's device
-    int32_t ds_start; // float index of the first delta slot
-    std::atomic<uint32_t> next_work{0};  // ring position of the next decode call
-    ndgsbp::DeviceTables dev;
-};

@@ -24,6 +24,7 @@
 // before the group, as eq. (1) prescribes for a group processed in parallel.
 #include <hip/hip_runtime.h>
 
+#include "ndgsbp_cn.h"
 #include "ndgsbp_internal.h"
 #include "ndgsbp_math.h"
 
@@ -127,72 +128,27 @@ __device__ __forceinline__ void load_visit(const Problem& p, int j0, int item, i
     }
 }
 
-// Value of the other lane of a lane pair (lanes 2i and 2i+1), by DPP.
-__device__ __forceinline__ uint32_t pair_swap(uint32_t x) {
-    return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0xB1, 0xF, 0xF, false);  // quad_perm [1,0,3,2]
-}
-
-// One lane's share of a CN visit: eq. (1) for its edges, then the add-back.
-// Per edge the lane forms eps = 1 - tanh(|x|/2) of its VN->CN message and
-// combines the eps of the other edges of the CN with (+) (ndgsbp_math.h) by
-// exclusive prefix and suffix; with H = 2 the two lanes of a CN exchange
-// their partial combinations and sign parities by DPP.
-// UNI: every CN has degree D, so no edge is padding.
+// One lane's share of a CN visit: eq. (1) for its edges (cn_core), then
+// the add-back into LDS.
 template <class M, int D, bool UNI, int H>
 __device__ __forceinline__ void cn_visit(const DecodeArgs& a, const Problem& p, const VisitRegs<D / H>& r,
                                          uint32_t h) {
     constexpr int DH = D / H;
     using R = Row<M, DH>;
     const uint32_t row = (uint32_t)p.l_offset + __umul24((uint32_t)(r.cn * H) + h, (uint32_t)R::kBytes);
-    float t[DH], lo[DH], e[DH];
-    uint32_t tb[DH];
-    uint32_t sall = 0;
+    float pv[DH], lo[DH], wv[DH];
+    bool real[DH], direct[DH];
+    typename M::T st[DH];
     R::load(row, lo);
 #pragma unroll
     for (int k = 0; k < DH; ++k) {
-        t[k] = lds_f32(r.pa[k]) - lo[k];  // VN->CN message, eq. (2)
-        // posteriors never hold -0.0, so the sign bit of t is the sign rule
-        tb[k] = __float_as_uint(t[k]);
-        e[k] = tanh_complement(exp2_hw(-clampf(fabsf(t[k]), a.ymin, a.ymax)));
-        if (!UNI) {
-            const bool real = r.pa[k] != p.pad_b;
-            e[k] = real ? e[k] : 0.0f;  // 0 is the identity of (+)
-            tb[k] = real ? tb[k] : 0u;
-        }
-        sall ^= tb[k];
+        pv[k] = lds_f32(r.pa[k]);
+        real[k] = r.pa[k] != p.pad_b;
+        direct[k] = r.ta[k] < p.ds_start_b;
     }
-    // exclusive combination over N(m) \ n: prefix (+) suffix (+ the partner's)
-    float pre[DH], c[DH];
-    if (DH > 1) pre[1] = e[0];
+    cn_core<M, DH, UNI, H>(pv, lo, real, direct, a.ymin, a.ymax, a.cmin, st, wv);
 #pragma unroll
-    for (int k = 2; k < DH; ++k) pre[k] = oplus(pre[k - 1], e[k - 1]);
-    float suf;
-    if (H == 2) {
-        const float mine = DH > 1 ? oplus(pre[DH - 1], e[DH - 1]) : e[0];
-        suf = __uint_as_float(pair_swap(__float_as_uint(mine)));
-        sall ^= pair_swap(sall);
-        c[DH - 1] = DH > 1 ? oplus(pre[DH - 1], suf) : suf;
-    } else {
-        suf = 0.0f;
-        c[DH - 1] = DH > 1 ? pre[DH - 1] : 0.0f;
-    }
-#pragma unroll
-    for (int k = DH - 2; k >= 0; --k) {
-        suf = (H == 1 && k == DH - 2) ? e[k + 1] : oplus(suf, e[k + 1]);
-        c[k] = k == 0 ? suf : oplus(pre[k], suf);
-    }
-    typename M::T st[DH];
-#pragma unroll
-    for (int k = 0; k < DH; ++k) {
-        const float mag = magnitude_from_complement(clampf(c[k], a.cmin, 1.0f));
-        const uint32_t out = __float_as_uint(mag) | ((sall ^ tb[k]) & 0x80000000u);
-        st[k] = M::pack(__uint_as_float(out));
-        const float ls = M::unpack(st[k]);
-        // posterior add-back (the VN's only edge in this group), or the
-        // delta new - old for the fix-up pass
-        const bool direct = r.ta[k] < p.ds_start_b;
-        lds_f32(r.ta[k]) = ls + (direct ? t[k] : -lo[k]);
-    }
+    for (int k = 0; k < DH; ++k) lds_f32(r.ta[k]) = wv[k];
     R::store(row, st);
 }
 
