@@ -167,6 +167,71 @@ def bench_batched(args, torch, nd, W, dev, log):
     }
 
 
+def bench_hbm(args, torch, nd, W, dev, log, sweep_llr, sweep_k):
+    """HBM tier: the sweep frames forced into the HBM tier, and a code beyond
+    LDS (QC rate 1/2, n=16896, 12 windows, overlap 176; all-zero codeword at
+    2.0 dB). Algorithmic HBM bytes per edge update: posterior read + write
+    (8 B) + message read + write (2 x message size)."""
+    from paper_1202_1060_amd import _native
+    from ldpcgen import make_frames
+    from ldpcgen.codes import qc_code, base_mask
+    stream = torch.cuda.current_stream(dev)
+
+    def run(dcode, x, max_iter, msg, steps, force):
+        F = x.shape[0]
+        out = nd.new_outputs(F, dcode.n, dev, want_post=False)
+        flags = (nd.msg_flag(msg) | nd.LDPC_FLAG_EARLY_STOP | (_native.LDPC_FLAG_TIER_HBM if force else 0))
+
+        def once():
+            nd.ldpc_decode(dcode.handle, x.data_ptr(), F, max_iter, flags, out["hard"].data_ptr(), 0,
+                           out["iters"].data_ptr(), out["syn_ok"].data_ptr(), stream.cuda_stream)
+        once()
+        torch.cuda.synchronize()
+        evs = []
+        for _ in range(steps):
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            once()
+            b.record(stream)
+            evs.append((a, b))
+        torch.cuda.synchronize()
+        ms = float(np.median([a.elapsed_time(b) for a, b in evs]))
+        iters = out["iters"].cpu().numpy()
+        eu = float(iters.astype(np.int64).sum()) * dcode.info["edge_updates"]
+        mb = 4 if msg == "fp32" else 2
+        gbs = eu * (8 + 2 * mb) / (ms * 1e-3) / 1e9
+        return dict(ms=ms, edge_updates_per_s=eu / (ms * 1e-3), mean_iters=float(iters.mean()),
+                    algorithmic_gb_s=gbs, hbm_frac=gbs / 8000.0), iters
+
+    rec = W.SWEEP
+    out = {"bytes_per_edge_update": "8 + 2 x message bytes"}
+    code = W.CODES[rec["code"]]()
+    dcode = nd.Code(code, windows=rec["windows"])
+    x = torch.from_numpy(sweep_llr).to(dev)
+    for msg in ("fp32", "fp16"):
+        r, iters = run(dcode, x, rec["max_iter"], msg, args.hbm_steps, True)
+        r["gbit_s"] = x.shape[0] * sweep_k / (r["ms"] * 1e-3) / 1e9
+        out[f"sweep_forced_{msg}"] = r
+        log(f"hbm tier, sweep {msg}: {r['gbit_s']:.2f} Gbit/s, {r['algorithmic_gb_s']:.0f} GB/s")
+    dcode.close()
+    del x
+    big = qc_code(base_mask("1/2", 1030), 704, 1030)
+    bcode = nd.Code(big, windows=(12, 176, 1))
+    llr, _ = make_frames(big.n, args.hbm_big_frames, 2.0, 0.5, seed=1031)
+    x = torch.from_numpy(llr).to(dev)
+    for msg in ("fp32", "fp16"):
+        r, _ = run(bcode, x, 20, msg, args.hbm_steps, False)
+        r["gbit_s"] = x.shape[0] * (big.n - big.m) / (r["ms"] * 1e-3) / 1e9
+        out[f"n16896_{msg}"] = r
+        log(f"hbm tier, n=16896 {msg}: {r['gbit_s']:.2f} Gbit/s, {r['algorithmic_gb_s']:.0f} GB/s")
+    out["n16896"] = {"frames": int(x.shape[0]), "lds_bytes_fp32": bcode.info["lds_bytes_fp32"],
+                     "lds_limit": bcode.info["lds_limit"], "info_bits_per_frame": big.n - big.m,
+                     "note": "all-zero codeword, 2.0 dB, 12 windows overlap 176, I_max 20, syndrome stop; info bits at the design rate (n - m)"}
+    bcode.close()
+    return out
+
+
 def bench_serving(args, torch, nd, W, dev, log):
     """Serving over the three resident QC codes: saturated throughput of the
     continuous-batching server, then Poisson arrivals at 0.5x and 0.8x of it
@@ -265,6 +330,9 @@ def main():
     ap.add_argument("--batch-steps", type=int, default=6)
     ap.add_argument("--tune-cache", default=None, help="autotuner cache file (default: user cache dir)")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving leg")
+    ap.add_argument("--no-hbm", action="store_true", help="skip the HBM-tier leg")
+    ap.add_argument("--hbm-steps", type=int, default=3)
+    ap.add_argument("--hbm-big-frames", type=int, default=32768)
     ap.add_argument("--serve-requests", type=int, default=30000)
     ap.add_argument("--serve-plain-requests", type=int, default=6000)
     ap.add_argument("--serve-verify", type=int, default=2000)
@@ -383,6 +451,8 @@ def main():
                                    "mean_iters": float(hiters.mean()), "fer": fer_table(hiters, hhard)}
     if not args.no_batched:
         result["batched"] = bench_batched(args, torch, nd, W, dev, log)
+    if not args.no_hbm:
+        result["hbm_tier"] = bench_hbm(args, torch, nd, W, dev, log, llr_np, enc.k)
     if not args.no_serving:
         result["serving"] = bench_serving(args, torch, nd, W, dev, log)
     if not args.no_cpu_baseline:
