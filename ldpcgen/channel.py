@@ -61,3 +61,15 @@ def make_frames(n: int, num_frames: int, ebn0_db: float, rate: float, seed,
         llr[lo - f0:hi - f0] = lb[lo - b * BLOCK:hi - b * BLOCK]
         cw[lo - f0:hi - f0] = cb[lo - b * BLOCK:hi - b * BLOCK]
     return llr, cw
+
+
+def device_all_zero_llr(n: int, num_frames: int, ebn0_db: float, rate: float, seed: int, device):
+    """All-zero codeword over BPSK/AWGN, generated on a torch device with a
+    seeded torch generator: L = (2 / sigma^2) (1 + sigma w). For error-rate
+    sweeps whose frame counts make host generation the bottleneck."""
+    import torch
+    sigma = ebn0_to_sigma(ebn0_db, rate)
+    g = torch.Generator(device=device)
+    g.manual_seed(int(seed))
+    w = torch.randn((num_frames, n), generator=g, device=device, dtype=torch.float32)
+    return (w * float(sigma) + 1.0) * float(2.0 / (sigma * sigma))

@@ -41,9 +41,23 @@ def encoder_for(code_key):
     return SystematicEncoder(CODES[code_key]())
 
 
+@functools.lru_cache(maxsize=None)
+def code_n504():
+    """(3,6)-regular, n=504, m=252, 4-cycle-free: stand-in for MacKay's (504,252)."""
+    return regular_code(504, 3, 6, seed=1040, girth6=True)
+
+
+@functools.lru_cache(maxsize=None)
+def code_n816():
+    """(4,6)-regular, n=816, m=544, 4-cycle-free: stand-in for MacKay's (816,*) code."""
+    return regular_code(816, 4, 6, seed=1041, girth6=True)
+
+
 CODES = {
     "n96": code_n96,
     "n2304": code_n2304,
+    "n504": code_n504,
+    "n816": code_n816,
     "qc2304": lambda: code_qc(2304, "1/2", 1002),
 }
 

@@ -1,0 +1,125 @@
+"""Error rates of BP, GSBP and NDGSBP at equal complexity (Sec. IV setup).
+
+The paper compares, on MacKay's (504,252) (3,6) code with G = 12 and on its
+(816,544) (4,6) code with G = 16:
+
+* standard BP (flooding: one group holding every CN), I_max = 1000;
+* GSBP (G disjoint CN groups), I_max = 1000;
+* NDGSBP (G groups by Step 1 with overlap ratio r = 0.4), with the iteration
+  cap lowered to M I_max / (M + (G - 1) N_G r), so that every decoder may
+  spend the same number of CN updates.
+
+MacKay's matrices are not available; seeded (3,6) n=504 and (4,6) n=816
+codes with the same sizes stand in for them. Frames carry the all-zero
+codeword (the decoders are symmetric), generated on the GPU; every decode
+runs the library's kernels with FP32 messages and syndrome stop. BER counts
+codeword bits. Groupings are drawn once per code (fixed over iterations).
+
+Usage: python -m paper_1202_1060_amd.experiments [--frames F] [--out FILE]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import sys
+import time
+
+import numpy as np
+import torch
+
+from . import Code, decode
+from .grouping import (group_size, step1_groups, disjoint_random_groups,
+                       equal_complexity_iterations)
+
+SETUPS = {
+    # code key, G, r, I_max of BP and GSBP, grouping seed
+    "n504": dict(G=12, r=0.4, I_max=1000, seed=3100),
+    "n816": dict(G=16, r=0.4, I_max=1000, seed=3101),
+}
+
+
+def clopper_pearson(k, n, alpha=0.05):
+    from scipy.stats import beta
+    lo = 0.0 if k == 0 else float(beta.ppf(alpha / 2, k, n - k + 1))
+    hi = 1.0 if k == n else float(beta.ppf(1 - alpha / 2, k + 1, n - k))
+    return lo, hi
+
+
+def decoders(code, setup):
+    """(name, groups, iteration cap, CN updates per iteration) of the three
+    decoders for one code."""
+    M = code.m
+    G, r, I = setup["G"], setup["r"], setup["I_max"]
+    rng = np.random.Generator(np.random.Philox(setup["seed"]))
+    N_G = group_size(M, G, r)
+    nd_groups = step1_groups(M, G, r, rng, N_G)
+    gs_groups = disjoint_random_groups(M, G, rng)
+    I_nd = equal_complexity_iterations(M, I, G, N_G, r)
+    return [("bp", [np.arange(M, dtype=np.int32)], I, M),
+            ("gsbp", gs_groups, I, M),
+            ("ndgsbp", nd_groups, I_nd, int(sum(len(g) for g in nd_groups)))], dict(N_G=N_G, I_ndgsbp=I_nd)
+
+
+def run(code_key, ebn0s, frames, device, log=None, chunk=1 << 18):
+    from ldpcgen import workloads as W
+    from ldpcgen.channel import device_all_zero_llr
+    from ldpcgen.gf2 import gf2_rank
+    code = W.CODES[code_key]()
+    K = code.n - gf2_rank(code.dense())
+    rate = K / code.n
+    setup = SETUPS[code_key]
+    decs, meta = decoders(code, setup)
+    out = dict(code=code_key, n=code.n, m=code.m, k=K, **setup, **meta, points=[])
+    for i, eb in enumerate(ebn0s):
+        row = dict(ebn0=eb)
+        for name, groups, cap, cn_per_iter in decs:
+            dcode = Code(code, groups=groups, device=device.index or 0)
+            fe = be = it = 0
+            t0 = time.perf_counter()
+            done = 0
+            while done < frames:
+                F = min(chunk, frames - done)
+                llr = device_all_zero_llr(code.n, F, eb, rate, 7000 + 100 * i + done // chunk, device)
+                o = decode(dcode, llr, cap, early_stop=True, want_post=False)
+                hard = o["hard"]
+                errs = hard.sum(dim=1, dtype=torch.int64)
+                fe += int((errs > 0).sum())
+                be += int(errs.sum())
+                it += int(o["iters"].sum(dtype=torch.int64))
+                done += F
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            dcode.close()
+            lo, hi = clopper_pearson(fe, frames)
+            row[name] = dict(fer=fe / frames, fer_ci95=[lo, hi], frame_errors=fe, ber=be / (frames * code.n),
+                             mean_iters=it / frames, cn_updates_per_frame=it / frames * cn_per_iter,
+                             iter_cap=cap, seconds=dt)
+            if log:
+                log(f"{code_key} {eb:.2f} dB {name:7s} FER {fe / frames:.3e} BER {be / (frames * code.n):.3e} "
+                    f"iters {it / frames:.2f} ({dt:.1f} s)")
+        out["points"].append(row)
+    return out
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--codes", nargs="+", default=["n504", "n816"])
+    ap.add_argument("--ebn0", nargs="+", type=float, default=[1.0, 1.5, 2.0, 2.5, 3.0])
+    ap.add_argument("--frames", type=int, default=1 << 20)
+    ap.add_argument("--out", default=None)
+    args = ap.parse_args(argv)
+    dev = torch.device("cuda", 0)
+
+    def log(*a):
+        print(*a, file=sys.stderr, flush=True)
+
+    res = [run(c, args.ebn0, args.frames, dev, log) for c in args.codes]
+    text = json.dumps(res, indent=1)
+    if args.out:
+        with open(args.out, "w") as f:
+            f.write(text)
+    print(text)
+
+
+if __name__ == "__main__":
+    main()

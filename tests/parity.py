@@ -14,7 +14,8 @@ moves by one float32 ulp; see oracle.decode_with_sensitivity):
   one-ulp input change is; frames the oracle decodes must still give
   identical decisions and iteration counts; on frames it does not decode the
   decoder must not decode either, and decision differences are counted and
-  capped at 2% of those frames.
+  capped at 2% of those frames, not counting frames whose FP64 decisions
+  themselves change under a one-ulp input change.
 Across all frames hard decisions must match on >= 99.99%, or every
 mismatch must sit in an undecoded, ill-conditioned frame.
 """
@@ -71,10 +72,16 @@ def compare(gpu, ref, rtol=RTOL, atol=ATOL, k_sens=K_SENS):
     assert np.array_equal(gpu["iters"][~conv], ref["iters"][~conv]), "iteration counts differ"
     # posteriors of every frame with matching decisions, widened where ill-conditioned
     assert np.all(pok[match]), f"posteriors out of the widened bound on {int((match & ~pok).sum())} frames"
+    # undecoded frames: a decision difference counts against the cap unless
+    # the FP64 oracle's own decisions on that frame change under a one-ulp
+    # input change (sens = inf): there the result is not determined at the
+    # precision of the float32 input, and no float32 decoder can match it
     nc = ~conv
-    nc_mis = int((~match & nc).sum())
+    chaotic = ~np.isfinite(sens)
+    nc_mis = int((~match & nc & ~chaotic).sum())
+    stats["undecoded_mismatch_chaotic"] = int((~match & nc & chaotic).sum())
     assert match.sum() >= MIN_FRAME_MATCH * F or nc_mis <= max(1, int(0.02 * nc.sum())), \
-        f"decisions match on {int(match.sum())}/{F} frames"
+        f"decisions match on {int(match.sum())}/{F} frames ({nc_mis} undecoded, oracle-stable)"
     return stats
 
 

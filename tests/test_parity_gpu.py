@@ -264,3 +264,17 @@ def test_lanes_per_check_node(lanes, msg):
             continue
         g, r = _run_both(code, rec["windows"], llr, rec["max_iter"], True, lanes=lanes)
         print("lanes", lanes, rec["name"], compare(g, r))
+
+
+def test_step1_random_grouping_meets_bar():
+    """The paper's own grouping (Step 1: random groups with overlap ratio
+    r = 0.4, G = 12, N_G = 34) on the n=504 stand-in, through explicit groups."""
+    from paper_1202_1060_amd.grouping import step1_groups
+    code = W.CODES["n504"]()
+    groups = step1_groups(code.m, 12, 0.4, np.random.Generator(np.random.Philox(3100)))
+    llr, _ = make_frames(code.n, 96, 2.0, 0.5, seed=61)
+    dcode = nd.Code(code, groups=groups)
+    g = gpu_decode(dcode, llr, 60, True)
+    dcode.close()
+    ref = oracle.decode_with_sensitivity(code, groups, llr, 60, True)
+    print("step1 n504", compare(g, ref))
