@@ -152,10 +152,61 @@ __device__ __forceinline__ void cn_visit(const DecodeArgs& a, const Problem& p, 
     R::store(row, st);
 }
 
+// Fix-up of one VN with c edges in the group: its posterior plus its c
+// deltas, added in slot order. The first four deltas are loaded together
+// (reads past the VN's slots land in the LDS allocation and are unused).
+__device__ __forceinline__ void fold_deltas(const Problem& p, uint2 e) {
+    const uint32_t v = e.x & 0xffffu, c = e.x >> 16;
+    const uint32_t d0 = p.ds_start_b + 4u * e.y;
+    float acc = lds_f32(4u * v);
+    float d[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) d[k] = lds_f32(d0 + 4u * k);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) acc = (uint32_t)k < c ? acc + d[k] : acc;
+    for (uint32_t k = 4; k < c; ++k) acc += lds_f32(d0 + 4u * k);
+    lds_f32(4u * v) = acc;
+}
+
+// Syndrome rows (LDS byte offsets of a check's posteriors, padded to SD)
+// that a lane keeps in registers for its first K checks tid, tid + nt, ...;
+// a check past m reads the constant +0 posterior n + 1 only.
+// K (measured on the n=2304 workload): one check with two lanes per CN, two
+// with one, none above degree 8; more registers per lane would cut the
+// workgroups resident per CU.
+template <int SD, int H>
+struct SynChecks {
+    static constexpr int value = SD > 8 ? 0 : H == 2 ? 1 : 2;
+};
+template <int SD, int K>
+struct SynRows {
+    uint32_t w[K > 0 ? K : 1][SD];
+    __device__ __forceinline__ void load(const Problem& p, int tid, int nt) {
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+            const int c = tid + j * nt;
+            if (c < p.m) {
+                const uint4* col = reinterpret_cast<const uint4*>(p.syn_col + (size_t)c * SD);
+#pragma unroll
+                for (int q = 0; q < SD / 4; ++q) {
+                    const uint4 x = col[q];
+                    w[j][4 * q] = x.x;
+                    w[j][4 * q + 1] = x.y;
+                    w[j][4 * q + 2] = x.z;
+                    w[j][4 * q + 3] = x.w;
+                }
+            } else {
+#pragma unroll
+                for (int k = 0; k < SD; ++k) w[j][k] = 4u * (uint32_t)(p.n + 1);
+            }
+        }
+    }
+};
+
 // Workgroup-size cap per degree variant: wide CNs need more registers per lane.
 template <int D>
 struct MaxThreads {
-    static constexpr int value = D >= 24 ? 256 : 1024;
+    static constexpr int value = D >= 24 ? 256 : D >= 16 ? 512 : 1024;
 };
 
 // Takes the next frame of the launch from its work counter (thread 0) and
@@ -251,6 +302,7 @@ template <class M, int D, bool UNI, int H, bool TABLE>
 __global__ __launch_bounds__(MaxThreads<D>::value) void ndgsbp_kernel(DecodeArgs a) {
     constexpr int DH = D / H;
     constexpr int SD = (D + 3) / 4 * 4;  // syndrome row stride (entries)
+    constexpr int SYNK = SynChecks<SD, H>::value;
     extern __shared__ __align__(16) unsigned char smem[];
     const int tid = threadIdx.x, nt = blockDim.x;
     // CN phase: this lane is half lh of visit vitem
@@ -279,6 +331,9 @@ __global__ __launch_bounds__(MaxThreads<D>::value) void ndgsbp_kernel(DecodeArgs
     VisitRegs<DH> nxt;
     bool have_nxt = vitem < table_i32(p.visit_ptr, 1);
     if (have_nxt) load_visit<DH, H>(p, 0, vitem, lh, nxt);
+    // rows of this lane's first SYNK checks, kept for the whole decode
+    SynRows<SD, SYNK> srow;
+    srow.load(p, tid, nt);
     __syncthreads();
 
     for (int step = 0; frame >= 0; ++step) {
@@ -289,6 +344,9 @@ __global__ __launch_bounds__(MaxThreads<D>::value) void ndgsbp_kernel(DecodeArgs
             const int jn0 = table_i32(p.visit_ptr, gn), jn1 = table_i32(p.visit_ptr, gn + 1);
             have_nxt = vitem < jn1 - jn0;
             if (have_nxt) load_visit<DH, H>(p, jn0, vitem, lh, nxt);
+            // this lane's first fix-up entry of the group, fetched before the CN phase
+            const int q0 = table_i32(p.fix_ptr, g), q1 = table_i32(p.fix_ptr, g + 1);
+            const uint2 fix0 = q0 + tid < q1 ? p.fix[q0 + tid] : make_uint2(0u, 0u);
             if (have_cur) cn_visit<M, D, UNI, H>(a, p, cur, lh);
             const int j0 = table_i32(p.visit_ptr, g), j1 = table_i32(p.visit_ptr, g + 1);
             for (int item = vitem + nvitem; item < j1 - j0; item += nvitem) {
@@ -297,16 +355,9 @@ __global__ __launch_bounds__(MaxThreads<D>::value) void ndgsbp_kernel(DecodeArgs
                 cn_visit<M, D, UNI, H>(a, p, extra, lh);
             }
             __syncthreads();
-            const int q0 = table_i32(p.fix_ptr, g), q1 = table_i32(p.fix_ptr, g + 1);
             if (q1 > q0) {
-                for (int q = q0 + tid; q < q1; q += nt) {
-                    const uint2 e = p.fix[q];
-                    const uint32_t v = e.x & 0xffffu, c = e.x >> 16;
-                    const uint32_t d0 = p.ds_start_b + 4u * e.y;
-                    float acc = lds_f32(4u * v);
-                    for (uint32_t k = 0; k < c; ++k) acc += lds_f32(d0 + 4u * k);
-                    lds_f32(4u * v) = acc;
-                }
+                if (q0 + tid < q1) fold_deltas(p, fix0);
+                for (int q = q0 + tid + nt; q < q1; q += nt) fold_deltas(p, p.fix[q]);
                 __syncthreads();
             }
         }
@@ -321,7 +372,19 @@ __global__ __launch_bounds__(MaxThreads<D>::value) void ndgsbp_kernel(DecodeArgs
         if (!check) continue;
         // the sign bit of a posterior is its hard decision (no -0.0); a lane
         // stops once any check has been seen to fail
-        for (int c = tid; c < p.m; c += nt) {
+        {
+            // the lane's first checks, from rows held in registers
+            uint32_t x = 0;
+#pragma unroll
+            for (int j = 0; j < SYNK; ++j) {
+                uint32_t par = 0;
+#pragma unroll
+                for (int k = 0; k < SD; ++k) par ^= __float_as_uint(lds_f32(srow.w[j][k]));
+                x |= par;
+            }
+            if (x >> 31) lds_i32(fl) = 1;
+        }
+        for (int c = tid + SYNK * nt; c < p.m; c += nt) {
             if (lds_i32(fl)) break;
             const uint4* col = reinterpret_cast<const uint4*>(p.syn_col + (size_t)c * SD);
             uint32_t x = 0;
@@ -351,6 +414,7 @@ __global__ __launch_bounds__(MaxThreads<D>::value) void ndgsbp_kernel(DecodeArgs
                     p = get_problem<TABLE>(a, pid);
                     have_nxt = vitem < table_i32(p.visit_ptr, 1);
                     if (have_nxt) load_visit<DH, H>(p, 0, vitem, lh, nxt);
+                    srow.load(p, tid, nt);
                 }
             }
             init_frame<M, D, H>(p, frame, tid, nt);
@@ -436,7 +500,7 @@ hipError_t dispatch(MsgKind kind, int dmax, bool uni, int lanes, A... args) {
 
 }  // namespace
 
-int max_threads_for_degree(int dmax) { return dmax >= 24 ? 256 : 1024; }
+int max_threads_for_degree(int dmax) { return dmax >= 24 ? 256 : dmax >= 16 ? 512 : 1024; }
 
 int message_row_bytes(MsgKind kind, int dmax, int lanes) {
     const int dh = dmax / lanes;
