@@ -56,6 +56,12 @@ def _load():
                                    ctypes.c_int, ctypes.POINTER(ctypes.c_double),
                                    ctypes.POINTER(ctypes.c_uint8), i32p,
                                    ctypes.POINTER(ctypes.c_uint8), ctypes.c_int]
+        lib.ref_decode_schedule.restype = ctypes.c_int
+        lib.ref_decode_schedule.argtypes = [ctypes.c_int, ctypes.c_int, i32p, i32p, ctypes.c_int, i32p, i32p,
+                                            ctypes.c_int, ctypes.POINTER(ctypes.c_float), ctypes.c_int,
+                                            ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_double),
+                                            ctypes.POINTER(ctypes.c_uint8), i32p,
+                                            ctypes.POINTER(ctypes.c_uint8), ctypes.c_int]
         lib.ref_phi_f64.restype = ctypes.c_double
         lib.ref_phi_f64.argtypes = [ctypes.c_double]
         lib.ref_boxplus.restype = ctypes.c_double
@@ -99,12 +105,16 @@ def _p(a, t):
     return a.ctypes.data_as(ctypes.POINTER(t))
 
 
-def decode(code, groups, llr, max_iter: int, early_stop: bool, nthreads: int = 0):
+def decode(code, groups, llr, max_iter: int, early_stop: bool, nthreads: int = 0,
+           groups_per_iteration: int = 0):
     """Run the FP64 oracle on float32 LLRs (F x n).
 
     ``code`` has m, n, row_ptr, col_idx; ``groups`` is a list of CN-id arrays
-    processed in order. Returns dict(post=float64 (F,n), hard=uint8 (F,n),
-    iters=int32 (F,), syn_ok=uint8 (F,), threads=int)."""
+    processed in order. With ``groups_per_iteration`` = Gp > 0 the groups
+    form blocks of Gp and iteration l uses block (l-1) mod (len(groups)/Gp)
+    (a new grouping every iteration, Step 4 back to Step 1). Returns
+    dict(post=float64 (F,n), hard=uint8 (F,n), iters=int32 (F,),
+    syn_ok=uint8 (F,), threads=int)."""
     lib = _load()
     llr = np.ascontiguousarray(llr, dtype=np.float32)
     if llr.ndim == 1:
@@ -119,8 +129,9 @@ def decode(code, groups, llr, max_iter: int, early_stop: bool, nthreads: int = 0
     iters = np.zeros(F, dtype=np.int32)
     syn = np.zeros(F, dtype=np.uint8)
     i32 = ctypes.c_int32
-    rc = lib.ref_decode(code.m, n, _p(row_ptr, i32), _p(col, i32), len(groups), _p(gptr, i32),
-                        _p(gcn, i32), _p(llr, ctypes.c_float), F, int(max_iter), int(bool(early_stop)),
+    rc = lib.ref_decode_schedule(code.m, n, _p(row_ptr, i32), _p(col, i32), len(groups), _p(gptr, i32),
+                        _p(gcn, i32), int(groups_per_iteration), _p(llr, ctypes.c_float), F, int(max_iter),
+                        int(bool(early_stop)),
                         _p(post, ctypes.c_double), _p(hard, ctypes.c_uint8), _p(iters, i32),
                         _p(syn, ctypes.c_uint8), int(nthreads))
     if rc < 0:
@@ -135,13 +146,14 @@ def perturb_one_ulp(llr, seed: int = 12345):
     return np.nextafter(llr, d).astype(np.float32)
 
 
-def decode_with_sensitivity(code, groups, llr, max_iter: int, early_stop: bool, nthreads: int = 0):
+def decode_with_sensitivity(code, groups, llr, max_iter: int, early_stop: bool, nthreads: int = 0,
+                            groups_per_iteration: int = 0):
     """Oracle result plus each frame's conditioning: ``sens[f]`` is the largest
     posterior change when every input LLR moves by one float32 ulp (inf when
     that already changes a hard decision). It measures how strongly the FP64
     decode amplifies rounding-sized input changes on that frame."""
-    ref = decode(code, groups, llr, max_iter, early_stop, nthreads)
-    ctl = decode(code, groups, perturb_one_ulp(llr), max_iter, early_stop, nthreads)
+    ref = decode(code, groups, llr, max_iter, early_stop, nthreads, groups_per_iteration)
+    ctl = decode(code, groups, perturb_one_ulp(llr), max_iter, early_stop, nthreads, groups_per_iteration)
     sens = np.abs(ctl["post"] - ref["post"]).max(axis=1)
     flip = np.any(ctl["hard"] != ref["hard"], axis=1) | (ctl["iters"] != ref["iters"])
     sens[flip] = np.inf

@@ -63,8 +63,10 @@ class ReachAlgebra:
         return self.vn(n, incoming)
 
 
-def run(rows, n, groups, n_iter, algebra, early_stop=False, trace=None):
-    """rows[m] = N(m) (VN ids); groups = ordered list of CN-id lists.
+def run(rows, n, groups, n_iter, algebra, early_stop=False, trace=None, groups_per_iteration=0):
+    """rows[m] = N(m) (VN ids); groups = ordered list of CN-id lists; with
+    groups_per_iteration = Gp > 0, iteration it (from 1) takes the groups
+    of block (it - 1) mod (len(groups) / Gp), Gp groups per block.
 
     ``trace``, if a list, receives after every sub-iteration a dict
     {vn: union (or list) of the CN->VN messages it currently holds}.
@@ -79,8 +81,10 @@ def run(rows, n, groups, n_iter, algebra, early_stop=False, trace=None):
     totals = hard = None
     ok = False
     used = n_iter
+    gp = groups_per_iteration or len(groups)
+    blocks = [groups[b:b + gp] for b in range(0, len(groups), gp)]
     for it in range(1, n_iter + 1):
-        for grp in groups:
+        for grp in blocks[(it - 1) % len(blocks)]:
             # (a) CN update: every CN of the group reads the pre-group lvc
             new = {}
             for m in grp:

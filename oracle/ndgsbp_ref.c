@@ -78,6 +78,7 @@ typedef struct {
     int32_t* iters;
     uint8_t* syn_ok;
     int nthreads;
+    int gper; /* groups per iteration: iteration l uses block (l-1) mod (G / gper) */
 } ref_job;
 
 typedef struct {
@@ -97,8 +98,10 @@ static void decode_frame(const ref_job* J, int f, double* Lch, double* Lcv, doub
     for (int n = 0; n < N; ++n) stamp[n] = -1;
     int used = J->max_iter, ok = 0;
     int visit = 0;
+    const int R = J->G / J->gper;
     for (int l = 1; l <= J->max_iter; ++l) {
-        for (int g = 0; g < J->G; ++g, ++visit) {
+        const int g0 = ((l - 1) % R) * J->gper;
+        for (int g = g0; g < g0 + J->gper; ++g, ++visit) {
             /* (a) CN update, eq. (1): Lvc is not written in this phase, so every
                CN of the group reads the pre-group VN->CN messages. */
             for (int q = J->gptr[g]; q < J->gptr[g + 1]; ++q) {
@@ -178,15 +181,21 @@ static void* worker(void* arg) {
 }
 
 /*
- * Decode F frames (llr: F x N float32, row-major). groups: gptr[G+1], gcn.
+ * Decode F frames (llr: F x N float32, row-major). groups: gptr[G+1], gcn,
+ * taken gper at a time: iteration l (from 1) processes groups
+ * b*gper .. b*gper + gper - 1 with b = (l - 1) mod (G / gper), i.e. a new
+ * grouping every iteration, cycling through G / gper of them (Step 4 returns
+ * to the grouping of Step 1); gper = 0 means all G groups every iteration.
  * Outputs (each may be NULL): post F x N doubles, hard F x N bytes,
  * iters F ints, syn_ok F bytes. nthreads <= 0 uses every online CPU.
  * Returns the number of threads used, or a negative value on bad input.
  */
-int ref_decode(int M, int N, const int32_t* row_ptr, const int32_t* col, int G, const int32_t* gptr,
-               const int32_t* gcn, const float* llr, int F, int max_iter, int early_stop, double* post,
-               uint8_t* hard, int32_t* iters, uint8_t* syn_ok, int nthreads) {
+int ref_decode_schedule(int M, int N, const int32_t* row_ptr, const int32_t* col, int G, const int32_t* gptr,
+                        const int32_t* gcn, int gper, const float* llr, int F, int max_iter, int early_stop,
+                        double* post, uint8_t* hard, int32_t* iters, uint8_t* syn_ok, int nthreads) {
     if (M <= 0 || N <= 0 || G <= 0 || F < 0 || max_iter < 1) return -1;
+    if (gper == 0) gper = G;
+    if (gper < 0 || G % gper) return -1;
     const int E = row_ptr[M];
     for (int m = 0; m < M; ++m)
         if (row_ptr[m + 1] < row_ptr[m]) return -1;
@@ -197,7 +206,7 @@ int ref_decode(int M, int N, const int32_t* row_ptr, const int32_t* col, int G, 
     if (F == 0) return 0;
     ref_job J;
     memset(&J, 0, sizeof J);
-    J.M = M; J.N = N; J.E = E; J.G = G;
+    J.M = M; J.N = N; J.E = E; J.G = G; J.gper = gper;
     J.row_ptr = row_ptr; J.col = col; J.gptr = gptr; J.gcn = gcn;
     J.llr = llr; J.F = F; J.max_iter = max_iter; J.early_stop = early_stop;
     J.post = post; J.hard = hard; J.iters = iters; J.syn_ok = syn_ok;
@@ -233,4 +242,12 @@ int ref_decode(int M, int N, const int32_t* row_ptr, const int32_t* col, int G, 
     free(J.vptr);
     free(J.vedge);
     return T;
+}
+
+/* The same with one grouping for every iteration. */
+int ref_decode(int M, int N, const int32_t* row_ptr, const int32_t* col, int G, const int32_t* gptr,
+               const int32_t* gcn, const float* llr, int F, int max_iter, int early_stop, double* post,
+               uint8_t* hard, int32_t* iters, uint8_t* syn_ok, int nthreads) {
+    return ref_decode_schedule(M, N, row_ptr, col, G, gptr, gcn, 0, llr, F, max_iter, early_stop, post, hard,
+                               iters, syn_ok, nthreads);
 }

@@ -168,6 +168,50 @@ def test_c_oracle_matches_literal_schedule(seed):
         assert bool(out["syn_ok"][f]) == ok
 
 
+def _rotated_windows(m, G, o, shift):
+    return [np.sort((np.asarray(g) + shift) % m).astype(np.int32) for g in oracle.windows(m, G, o, wrap=True)]
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_c_oracle_matches_literal_regrouping(seed):
+    """A new grouping every iteration (Step 4 returns to Step 1): the C
+    oracle's schedule against the independent literal decoder."""
+    rng = np.random.default_rng(300 + seed)
+    n = int(rng.integers(16, 30))
+    m = n // 2
+    rows = _random_code(rng, n, m)
+    code = _code_from_rows(rows, n)
+    G, o = int(rng.integers(2, 4)), 1
+    sched = []
+    for b in range(3):
+        sched += _rotated_windows(m, G, o, int(rng.integers(0, m)))
+    llr = rng.normal(0.6, 1.0, size=(3, n)).astype(np.float32)
+    out = oracle.decode(code, sched, llr, max_iter=5, early_stop=False, nthreads=2, groups_per_iteration=G)
+    for f in range(3):
+        tot, hard, _, ok = literal.run(rows, n, [list(g) for g in sched], 5,
+                                       literal.RealAlgebra(llr[f].astype(np.float64)), groups_per_iteration=G)
+        np.testing.assert_allclose(out["post"][f], tot, rtol=1e-9, atol=1e-9)
+        assert list(out["hard"][f]) == hard
+
+
+def test_regrouping_reductions():
+    """Repeating one grouping R times is that grouping; one iteration uses
+    the first block only; different blocks change the result."""
+    rng = np.random.default_rng(11)
+    code = regular_code(96, 3, 6, seed=1000)
+    llr, _ = make_frames(96, 8, 1.5, 0.5, seed=5)
+    A = _rotated_windows(code.m, 4, 2, 0)
+    B = _rotated_windows(code.m, 4, 2, 7)
+    plain = oracle.decode(code, A, llr, 6, False)
+    rep = oracle.decode(code, A + A + A, llr, 6, False, groups_per_iteration=4)
+    assert np.array_equal(plain["post"], rep["post"])
+    one = oracle.decode(code, A + B, llr, 1, False, groups_per_iteration=4)
+    assert np.array_equal(one["post"], oracle.decode(code, A, llr, 1, False)["post"])
+    two = oracle.decode(code, A + B, llr, 2, False, groups_per_iteration=4)
+    assert not np.array_equal(two["post"], oracle.decode(code, A, llr, 2, False)["post"])
+    assert rng is not None
+
+
 # ------------------------------------------------------ textbook special cases
 
 def _tanh_cn(x):
