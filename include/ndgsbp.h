@@ -57,13 +57,19 @@ typedef struct {
     const int32_t* col_idx; /* host, nnz entries   */
 } ldpc_h_csr;
 
-/* CN grouping (Sec. II-A, Step 1), processed in this order every iteration.
+/* CN grouping (Sec. II-A, Step 1), processed in this order every iteration
+ * (or, with groups_per_iteration, a new grouping every iteration).
  * WINDOWS: group g = CNs start_g .. start_g + len_g - 1 with
  *   start_g = floor(g*m/G), len_g = start_{g+1} - start_g + overlap,
  *   indices mod m when wrap != 0 (the last window then overlaps the first);
  *   with wrap == 0 the last window ends at m.
  * EXPLICIT: group g = group_cn[group_ptr[g] .. group_ptr[g+1]) (host).
- * Every CN must appear in some group and at most once within a group. */
+ *   groups_per_iteration = Gp > 0 splits the groups into R = num_groups / Gp
+ *   blocks; iteration l (from 1) processes block (l - 1) mod R, so each
+ *   iteration can use a fresh grouping (Step 4 returns to Step 1). 0: all
+ *   groups every iteration. Decodes with R > 1 run in the LDS tier only.
+ * Every CN must appear in some group (of every block) and at most once
+ * within a group. */
 typedef struct {
     int32_t kind;
     int32_t num_groups;
@@ -71,6 +77,7 @@ typedef struct {
     int32_t wrap;              /* WINDOWS only */
     const int32_t* group_ptr;  /* EXPLICIT only, host, num_groups + 1 */
     const int32_t* group_cn;   /* EXPLICIT only, host                 */
+    int32_t groups_per_iteration; /* EXPLICIT only; 0 = num_groups   */
 } ldpc_grouping;
 
 /* Sizes of a created code, for callers that size buffers or count work. */
@@ -78,8 +85,8 @@ typedef struct {
     int32_t m, n;
     int64_t nnz;
     int32_t num_groups;
-    int64_t cn_visits;       /* sum of group sizes: CN updates per iteration  */
-    int64_t edge_updates;    /* sum of CN degrees over all visits             */
+    int64_t cn_visits;       /* CN updates per iteration (mean over blocks)   */
+    int64_t edge_updates;    /* edge updates per iteration (mean over blocks) */
     int32_t max_cn_degree;
     int32_t max_vn_degree;
     int32_t device;
@@ -90,6 +97,7 @@ typedef struct {
     int32_t lanes_fp32;      /* lanes per CN visit used with FP32 messages    */
     int32_t lanes_fp16;      /* ... with FP16 messages                        */
     int32_t lanes_bf16;      /* ... with BF16 messages                        */
+    int32_t groups_per_iteration;
 } ldpc_code_info;
 
 /* Validate H and the grouping, build the device tables and upload them to

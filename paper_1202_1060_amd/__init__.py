@@ -41,11 +41,13 @@ def ldpc_last_error() -> str:
     return _native.load().ldpc_last_error().decode(errors="replace")
 
 
-def ldpc_code_create(m, n, row_ptr, col_idx, *, windows=None, groups=None, device=0):
+def ldpc_code_create(m, n, row_ptr, col_idx, *, windows=None, groups=None, device=0,
+                     groups_per_iteration=0):
     """Create a device code handle (see include/ndgsbp.h).
 
-    ``windows=(G, overlap, wrap)`` or ``groups=[CN-id arrays]`` (in order).
-    Returns the opaque handle (int)."""
+    ``windows=(G, overlap, wrap)`` or ``groups=[CN-id arrays]`` (in order;
+    with ``groups_per_iteration`` = Gp, iteration l uses the l-th block of
+    Gp groups, cyclically). Returns the opaque handle (int)."""
     rp, ci = _i32(row_ptr), _i32(col_idx)
     h = _native.ldpc_h_csr(int(m), int(n), int(len(ci)), _ptr(rp), _ptr(ci))
     if (windows is None) == (groups is None):
@@ -53,12 +55,13 @@ def ldpc_code_create(m, n, row_ptr, col_idx, *, windows=None, groups=None, devic
     keep = []
     if windows is not None:
         G, o, wrap = windows
-        g = _native.ldpc_grouping(LDPC_GROUPS_WINDOWS, int(G), int(o), int(bool(wrap)), None, None)
+        g = _native.ldpc_grouping(LDPC_GROUPS_WINDOWS, int(G), int(o), int(bool(wrap)), None, None, 0)
     else:
         gptr = _i32(np.concatenate([[0], np.cumsum([len(x) for x in groups])]))
         gcn = _i32(np.concatenate([np.asarray(x) for x in groups]) if len(groups) else [])
         keep += [gptr, gcn]
-        g = _native.ldpc_grouping(LDPC_GROUPS_EXPLICIT, len(groups), 0, 0, _ptr(gptr), _ptr(gcn))
+        g = _native.ldpc_grouping(LDPC_GROUPS_EXPLICIT, len(groups), 0, 0, _ptr(gptr), _ptr(gcn),
+                                  int(groups_per_iteration))
     out = ctypes.c_void_p()
     _native.check(_native.load().ldpc_code_create(ctypes.byref(h), ctypes.byref(g), int(device), ctypes.byref(out)))
     return out.value
@@ -96,10 +99,11 @@ class Code:
     """Owns a device code handle. ``code`` is any object with m, n, row_ptr,
     col_idx (e.g. ldpcgen.Code)."""
 
-    def __init__(self, code, *, windows=None, groups=None, device=0):
+    def __init__(self, code, *, windows=None, groups=None, device=0, groups_per_iteration=0):
         self.m, self.n = int(code.m), int(code.n)
         self.handle = ldpc_code_create(code.m, code.n, code.row_ptr, code.col_idx,
-                                       windows=windows, groups=groups, device=device)
+                                       windows=windows, groups=groups, device=device,
+                                       groups_per_iteration=groups_per_iteration)
         self.info = ldpc_code_query(self.handle)
         self.device = device
 

@@ -40,7 +40,7 @@ class ldpc_h_csr(ctypes.Structure):
 class ldpc_grouping(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("num_groups", ctypes.c_int32),
                 ("overlap", ctypes.c_int32), ("wrap", ctypes.c_int32),
-                ("group_ptr", _i32p), ("group_cn", _i32p)]
+                ("group_ptr", _i32p), ("group_cn", _i32p), ("groups_per_iteration", ctypes.c_int32)]
 
 
 class ldpc_code_info(ctypes.Structure):
@@ -50,7 +50,7 @@ class ldpc_code_info(ctypes.Structure):
                 ("max_vn_degree", ctypes.c_int32), ("device", ctypes.c_int32),
                 ("lds_bytes_fp32", ctypes.c_int64), ("lds_bytes_16", ctypes.c_int64),
                 ("lds_limit", ctypes.c_int64), ("lanes_fp32", ctypes.c_int32), ("lanes_fp16", ctypes.c_int32),
-                ("lanes_bf16", ctypes.c_int32)]
+                ("lanes_bf16", ctypes.c_int32), ("groups_per_iteration", ctypes.c_int32)]
 
 
 class ldpc_problem(ctypes.Structure):

@@ -37,7 +37,8 @@ struct ldpc_code {
     int32_t device;
     int32_t m, n;
     int64_t nnz;
-    int32_t G;
+    int32_t G;  // groups per iteration
+    int32_t R;  // iteration blocks: iteration l uses groups ((l-1) mod R) * G ..
     int64_t cn_visits;
     int64_t edge_updates;
     int32_t max_cn_degree;

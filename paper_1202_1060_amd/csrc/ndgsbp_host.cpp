@@ -120,19 +120,30 @@ int expand_groups(const ldpc_grouping* g, int m, std::vector<std::vector<int32_t
     } else {
         return fail(LDPC_EINVAL, "unknown grouping kind");
     }
-    // no CN twice in a group; every CN in some group
+    // iteration blocks: all groups, or groups_per_iteration at a time
+    const int gpi = g->groups_per_iteration;
+    if (gpi < 0) return fail(LDPC_EINVAL, "groups_per_iteration < 0");
+    if (gpi > 0 && g->kind != LDPC_GROUPS_EXPLICIT)
+        return fail(LDPC_EINVAL, "groups_per_iteration needs explicit groups");
+    const int per = gpi > 0 ? gpi : (int)out.size();
+    if ((int)out.size() % per) return fail(LDPC_EINVAL, "num_groups is not a multiple of groups_per_iteration");
+    // no CN twice in a group; every CN in some group of every iteration block
     std::vector<int32_t> stamp(m, -1);
-    std::vector<char> covered(m, 0);
+    std::vector<int32_t> covered(m, -1);
     for (size_t k = 0; k < out.size(); ++k) {
         if (out[k].empty()) return fail(LDPC_EINVAL, "empty group");
+        const int32_t blk = (int32_t)(k / per);
         for (int32_t c : out[k]) {
             if (stamp[c] == (int32_t)k) return fail(LDPC_EINVAL, "CN repeated within a group");
             stamp[c] = (int32_t)k;
-            covered[c] = 1;
+            covered[c] = blk;
         }
+        if ((k + 1) % per == 0)
+            for (int c = 0; c < m; ++c)
+                if (covered[c] != blk)
+                    return fail(LDPC_EINVAL, "CN " + std::to_string(c) + " belongs to no group" +
+                                                 (gpi > 0 ? " of iteration block " + std::to_string(blk) : ""));
     }
-    for (int c = 0; c < m; ++c)
-        if (!covered[c]) return fail(LDPC_EINVAL, "CN " + std::to_string(c) + " belongs to no group");
     return LDPC_OK;
 }
 
@@ -232,6 +243,7 @@ Problem make_problem(const ldpc_code* c, const Layout& lay, const float* llr, in
     p.n = c->n;
     p.m = c->m;
     p.G = c->G;
+    p.R = c->R;
     p.max_iter = max_iter;
     p.first = 0;
     p.num_frames = num_frames;
@@ -520,6 +532,9 @@ int decode_hbm(ldpc_code* c, const float* llr, int32_t num_frames, int32_t max_i
     const MsgKind kind = msg_kind(flags);
     const Layout& lay = c->lay[0];
     if (!lay.valid) return fail(LDPC_EUNSUPPORTED, "no one-lane tables for the HBM tier");
+    if (c->R > 1)
+        return fail(LDPC_EUNSUPPORTED, "the HBM tier decodes its 64 frames of a tile at different iterations: "
+                                       "one grouping for every iteration only");
     const int slots = hbm_slots();
     const int waves = std::max(1, std::min(hbm_max_threads(lay.D) / 64, c->max_group_visits));
     const int threads = 64 * waves;
@@ -636,7 +651,8 @@ int ldpc_code_create(const ldpc_h_csr* H, const ldpc_grouping* grouping, int32_t
     c->m = m;
     c->n = n;
     c->nnz = H->nnz;
-    c->G = (int32_t)groups.size();
+    c->R = (grouping->groups_per_iteration > 0) ? (int32_t)groups.size() / grouping->groups_per_iteration : 1;
+    c->G = (int32_t)groups.size() / c->R;
     c->max_cn_degree = maxd;
     c->max_vn_degree = n ? *std::max_element(vdeg.begin(), vdeg.end()) : 0;
 
@@ -812,9 +828,10 @@ int ldpc_code_query(ldpc_code_t c, ldpc_code_info* info) {
     info->m = c->m;
     info->n = c->n;
     info->nnz = c->nnz;
-    info->num_groups = c->G;
-    info->cn_visits = c->cn_visits;
-    info->edge_updates = c->edge_updates;
+    info->num_groups = c->G * c->R;
+    info->cn_visits = c->cn_visits / c->R;
+    info->edge_updates = c->edge_updates / c->R;
+    info->groups_per_iteration = c->G;
     info->max_cn_degree = c->max_cn_degree;
     info->max_vn_degree = c->max_vn_degree;
     info->device = c->device;

@@ -72,7 +72,7 @@ struct Problem {
     uint32_t ds_start_b;  // byte offset of the first delta slot
     uint32_t pad_b;       // byte offset of the scratch posterior n of padding edges
     int32_t l_offset;     // byte offset of the message rows
-    int32_t reserved;
+    int32_t R;            // iteration blocks of G groups: iteration l uses block (l-1) mod R
 };
 
 // Kernel arguments. A launch decodes p0 (table == nullptr) or the nprob

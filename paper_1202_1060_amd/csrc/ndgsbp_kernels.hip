@@ -337,10 +337,15 @@ __global__ __launch_bounds__(MaxThreads<D>::value) void ndgsbp_kernel(DecodeArgs
     __syncthreads();
 
     for (int step = 0; frame >= 0; ++step) {
-        for (int g = 0; g < p.G; ++g) {
+        // this iteration's block of groups (a new grouping every iteration
+        // when the code has R > 1 blocks), and the first group of the next
+        const int gb = p.R > 1 ? (used % p.R) * p.G : 0;
+        const int gb_next = p.R > 1 ? ((used + 1) % p.R) * p.G : 0;
+        for (int gi = 0; gi < p.G; ++gi) {
+            const int g = gb + gi;
             const VisitRegs<DH> cur = nxt;
             const bool have_cur = have_nxt;
-            const int gn = g + 1 == p.G ? 0 : g + 1;
+            const int gn = gi + 1 == p.G ? gb_next : g + 1;
             const int jn0 = table_i32(p.visit_ptr, gn), jn1 = table_i32(p.visit_ptr, gn + 1);
             have_nxt = vitem < jn1 - jn0;
             if (have_nxt) load_visit<DH, H>(p, jn0, vitem, lh, nxt);
@@ -415,7 +420,14 @@ __global__ __launch_bounds__(MaxThreads<D>::value) void ndgsbp_kernel(DecodeArgs
                     have_nxt = vitem < table_i32(p.visit_ptr, 1);
                     if (have_nxt) load_visit<DH, H>(p, 0, vitem, lh, nxt);
                     srow.load(p, tid, nt);
+                } else if (p.R > 1) {
+                    // the next iteration's first group was fetched; a new frame starts at block 0
+                    have_nxt = vitem < table_i32(p.visit_ptr, 1);
+                    if (have_nxt) load_visit<DH, H>(p, 0, vitem, lh, nxt);
                 }
+            } else if (p.R > 1) {
+                have_nxt = vitem < table_i32(p.visit_ptr, 1);
+                if (have_nxt) load_visit<DH, H>(p, 0, vitem, lh, nxt);
             }
             init_frame<M, D, H>(p, frame, tid, nt);
         }

@@ -13,7 +13,9 @@ MacKay's matrices are not available; seeded (3,6) n=504 and (4,6) n=816
 codes with the same sizes stand in for them. Frames carry the all-zero
 codeword (the decoders are symmetric), generated on the GPU; every decode
 runs the library's kernels with FP32 messages and syndrome stop. BER counts
-codeword bits. Groupings are drawn once per code (fixed over iterations).
+codeword bits. NDGSBP runs twice: with one Step-1 grouping for the whole
+decode, and with a fresh Step-1 grouping for every iteration (as Step 4's
+return to Step 1 reads), drawn ahead of time up to the iteration cap.
 
 Usage: python -m paper_1202_1060_amd.experiments [--frames F] [--out FILE]
 """
@@ -46,8 +48,10 @@ def clopper_pearson(k, n, alpha=0.05):
 
 
 def decoders(code, setup):
-    """(name, groups, iteration cap, CN updates per iteration) of the three
-    decoders for one code."""
+    """(name, groups, groups per iteration, iteration cap, CN updates per
+    iteration) of the decoders for one code: BP, GSBP, NDGSBP with one
+    Step-1 grouping, and NDGSBP with a fresh Step-1 grouping for every
+    iteration up to its cap (Step 4 returns to Step 1)."""
     M = code.m
     G, r, I = setup["G"], setup["r"], setup["I_max"]
     rng = np.random.Generator(np.random.Philox(setup["seed"]))
@@ -55,9 +59,14 @@ def decoders(code, setup):
     nd_groups = step1_groups(M, G, r, rng, N_G)
     gs_groups = disjoint_random_groups(M, G, rng)
     I_nd = equal_complexity_iterations(M, I, G, N_G, r)
-    return [("bp", [np.arange(M, dtype=np.int32)], I, M),
-            ("gsbp", gs_groups, I, M),
-            ("ndgsbp", nd_groups, I_nd, int(sum(len(g) for g in nd_groups)))], dict(N_G=N_G, I_ndgsbp=I_nd)
+    sched = []
+    for _ in range(I_nd):
+        sched += step1_groups(M, G, r, rng, N_G)
+    per_iter = int(sum(len(g) for g in nd_groups))
+    return [("bp", [np.arange(M, dtype=np.int32)], 0, I, M),
+            ("gsbp", gs_groups, 0, I, M),
+            ("ndgsbp", nd_groups, 0, I_nd, per_iter),
+            ("ndgsbp_regroup", sched, G, I_nd, per_iter)], dict(N_G=N_G, I_ndgsbp=I_nd)
 
 
 def run(code_key, ebn0s, frames, device, log=None, chunk=1 << 18):
@@ -72,8 +81,8 @@ def run(code_key, ebn0s, frames, device, log=None, chunk=1 << 18):
     out = dict(code=code_key, n=code.n, m=code.m, k=K, **setup, **meta, points=[])
     for i, eb in enumerate(ebn0s):
         row = dict(ebn0=eb)
-        for name, groups, cap, cn_per_iter in decs:
-            dcode = Code(code, groups=groups, device=device.index or 0)
+        for name, groups, gpi, cap, cn_per_iter in decs:
+            dcode = Code(code, groups=groups, device=device.index or 0, groups_per_iteration=gpi)
             fe = be = it = 0
             t0 = time.perf_counter()
             done = 0

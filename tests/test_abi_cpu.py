@@ -145,3 +145,17 @@ def test_batch_argument_errors(nd):
 def test_destroy_null_is_ok(nd):
     from paper_1202_1060_amd import _native
     assert _native.load().ldpc_code_destroy(None) == 0
+
+
+def test_regrouping_argument_checks(nd):
+    """groups_per_iteration: explicit groups only, a divisor of num_groups,
+    every CN covered by every block (checked before any device work)."""
+    m, n = 4, 8
+    rp, ci = [0, 2, 4, 6, 8], [0, 1, 2, 3, 4, 5, 6, 7]
+    with pytest.raises(nd.LdpcError) as ei:   # 3 groups, 2 per iteration
+        nd.ldpc_code_create(m, n, rp, ci, groups=[[0, 1], [2, 3], [0, 1, 2, 3]], groups_per_iteration=2)
+    assert ei.value.code == nd.LDPC_EINVAL
+    with pytest.raises(nd.LdpcError) as ei:   # block 1 misses CN 3
+        nd.ldpc_code_create(m, n, rp, ci, groups=[[0, 1], [2, 3], [0, 1], [2]], groups_per_iteration=2)
+    assert ei.value.code == nd.LDPC_EINVAL
+    assert "block 1" in nd.ldpc_last_error()

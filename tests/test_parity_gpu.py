@@ -278,3 +278,33 @@ def test_step1_random_grouping_meets_bar():
     dcode.close()
     ref = oracle.decode_with_sensitivity(code, groups, llr, 60, True)
     print("step1 n504", compare(g, ref))
+
+
+def test_regrouping_every_iteration_meets_bar():
+    """Step 4 returns to Step 1: a new random Step-1 grouping every
+    iteration (R = 5 drawn groupings, cycled), against the oracle's schedule;
+    a batch gives the same as the single decode; the HBM tier refuses it."""
+    from paper_1202_1060_amd.grouping import step1_groups
+    code = W.CODES["n504"]()
+    rng = np.random.Generator(np.random.Philox(3200))
+    sched = []
+    for _ in range(5):
+        sched += step1_groups(code.m, 12, 0.4, rng)
+    llr, _ = make_frames(code.n, 96, 2.0, 0.5, seed=62)
+    dcode = nd.Code(code, groups=sched, groups_per_iteration=12)
+    assert dcode.info["groups_per_iteration"] == 12 and dcode.info["num_groups"] == 60
+    g = gpu_decode(dcode, llr, 23, True)
+    ref = oracle.decode_with_sensitivity(code, sched, llr, 23, True, groups_per_iteration=12)
+    print("regroup n504", compare(g, ref))
+    x = torch.from_numpy(llr).to("cuda:0")
+    outs = nd.decode_batched([nd.Problem(dcode, x, 23)], msg="fp32")
+    torch.cuda.synchronize()
+    for k in ("hard", "post", "iters", "syn_ok"):
+        assert np.array_equal(outs[0][k].cpu().numpy(), g[k]), k
+    from paper_1202_1060_amd import _native
+    o = nd.new_outputs(96, code.n, x.device)
+    with pytest.raises(nd.LdpcError) as ei:
+        nd.ldpc_decode(dcode.handle, x.data_ptr(), 96, 23, _native.LDPC_FLAG_TIER_HBM, o["hard"].data_ptr(), 0,
+                       o["iters"].data_ptr(), 0, torch.cuda.current_stream().cuda_stream)
+    assert ei.value.code == nd.LDPC_EUNSUPPORTED
+    dcode.close()
