@@ -336,11 +336,11 @@ __global__ __launch_bounds__(MaxThreads<D>::value) void ndgsbp_kernel(DecodeArgs
     srow.load(p, tid, nt);
     __syncthreads();
 
+    // first group of this iteration's block (a new grouping every iteration
+    // when the code has R > 1 blocks of G groups)
+    int gb = 0;
     for (int step = 0; frame >= 0; ++step) {
-        // this iteration's block of groups (a new grouping every iteration
-        // when the code has R > 1 blocks), and the first group of the next
-        const int gb = p.R > 1 ? (used % p.R) * p.G : 0;
-        const int gb_next = p.R > 1 ? ((used + 1) % p.R) * p.G : 0;
+        const int gb_next = gb + p.G < p.G * p.R ? gb + p.G : 0;
         for (int gi = 0; gi < p.G; ++gi) {
             const int g = gb + gi;
             const VisitRegs<DH> cur = nxt;
@@ -366,6 +366,7 @@ __global__ __launch_bounds__(MaxThreads<D>::value) void ndgsbp_kernel(DecodeArgs
                 __syncthreads();
             }
         }
+        gb = gb_next;
         // a4: hard decisions (d = 1 iff total < 0) and the syndrome over all checks
         used += 1;
         const uint32_t fl = sh + 4u + 4u * (step & 1);        // this step's flag
@@ -411,24 +412,23 @@ __global__ __launch_bounds__(MaxThreads<D>::value) void ndgsbp_kernel(DecodeArgs
         frame = __builtin_amdgcn_readfirstlane(lds_i32(sh));
         used = 0;
         if (frame >= 0) {
+            // a new frame starts at block 0: the prefetched first group is
+            // right unless the block changed or the problem did
+            bool reload = gb != 0;
             if constexpr (TABLE) {
                 const int np = __builtin_amdgcn_readfirstlane(lds_i32(sh + 12));
                 if (np != pid) {
-                    // another problem: its tables, and its first group fetched again
                     pid = np;
                     p = get_problem<TABLE>(a, pid);
-                    have_nxt = vitem < table_i32(p.visit_ptr, 1);
-                    if (have_nxt) load_visit<DH, H>(p, 0, vitem, lh, nxt);
                     srow.load(p, tid, nt);
-                } else if (p.R > 1) {
-                    // the next iteration's first group was fetched; a new frame starts at block 0
-                    have_nxt = vitem < table_i32(p.visit_ptr, 1);
-                    if (have_nxt) load_visit<DH, H>(p, 0, vitem, lh, nxt);
+                    reload = true;
                 }
-            } else if (p.R > 1) {
+            }
+            if (reload) {
                 have_nxt = vitem < table_i32(p.visit_ptr, 1);
                 if (have_nxt) load_visit<DH, H>(p, 0, vitem, lh, nxt);
             }
+            gb = 0;
             init_frame<M, D, H>(p, frame, tid, nt);
         }
         __syncthreads();
