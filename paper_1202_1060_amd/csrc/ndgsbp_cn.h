@@ -20,19 +20,19 @@ __device__ __forceinline__ uint32_t pair_swap(uint32_t x) {
 //   pv[k]     posterior of edge k's VN (log2 units; never -0.0)
 //   lo[k]     the edge's old CN->VN message (as stored, widened)
 //   real[k]   edge k is not padding (ignored when UNI)
-//   direct[k] the VN has no other edge in the group: the posterior itself
-//             is written back, else a delta
 // Per edge the lane forms the VN->CN message t = pv - lo (eq. (2), the
 // posterior being the total of eq. (3)) and eps = 1 - tanh(|t|/2); the eps of
 // the other edges of the CN are combined with (+) (ndgsbp_math.h) by exclusive
 // prefix and suffix; with H = 2 the two lanes exchange their partial
 // combinations and sign parities by DPP. Outputs: st[k] the new message in
-// the storage format, wv[k] the value the edge writes back: new + t (the
-// posterior) or new - old (a delta).
+// the storage format, wv[k] = new + t, the VN's posterior as this edge alone
+// would leave it. A VN with no other edge in the group takes wv as its
+// posterior; for a VN with several, wv - pv is this edge's change (new - old
+// up to rounding) and the fix-up adds the changes of all its edges.
 template <class M, int DH, bool UNI, int H>
 __device__ __forceinline__ void cn_core(const float (&pv)[DH], const float (&lo)[DH], const bool (&real)[DH],
-                                        const bool (&direct)[DH], float ymin, float ymax, float cmin,
-                                        typename M::T (&st)[DH], float (&wv)[DH]) {
+                                        float ymin, float ymax, float cmin, typename M::T (&st)[DH],
+                                        float (&wv)[DH]) {
     float t[DH], e[DH];
     uint32_t tb[DH];
     uint32_t sall = 0;
@@ -74,7 +74,7 @@ __device__ __forceinline__ void cn_core(const float (&pv)[DH], const float (&lo)
         const uint32_t out = __float_as_uint(mag) | ((sall ^ tb[k]) & 0x80000000u);
         st[k] = M::pack(__uint_as_float(out));
         const float ls = M::unpack(st[k]);
-        wv[k] = ls + (direct[k] ? t[k] : -lo[k]);
+        wv[k] = ls + t[k];
     }
 }
 

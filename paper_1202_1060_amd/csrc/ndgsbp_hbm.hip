@@ -126,7 +126,7 @@ __global__ __launch_bounds__(HbmMaxThreads<D>::value) void ndgsbp_hbm_kernel(Hbm
                 const int cn = tbl_i32(p.vcn, j);
                 const bool zero_old = fresh && tbl_u32(a.vfirst, j);
                 float pv[D], lo[D], wvals[D];
-                bool real[D], direct[D];
+                bool real[D];
                 T st[D];
                 uint32_t pa[D], ta[D];
 #pragma unroll
@@ -141,9 +141,8 @@ __global__ __launch_bounds__(HbmMaxThreads<D>::value) void ndgsbp_hbm_kernel(Hbm
                     pv[k] = fw[(size_t)pa[k] * (kSlots / 4) + lane];
                     lo[k] = zero_old ? 0.0f : M::unpack(row[k * kSlots]);
                     real[k] = pa[k] != p.pad_b;
-                    direct[k] = ta[k] < p.ds_start_b;
                 }
-                cn_core<M, D, UNI, 1>(pv, lo, real, direct, a.ymin, a.ymax, a.cmin, st, wvals);
+                cn_core<M, D, UNI, 1>(pv, lo, real, a.ymin, a.ymax, a.cmin, st, wvals);
 #pragma unroll
                 for (int k = 0; k < D; ++k) {
                     fw[(size_t)ta[k] * (kSlots / 4) + lane] = wvals[k];
@@ -158,8 +157,9 @@ __global__ __launch_bounds__(HbmMaxThreads<D>::value) void ndgsbp_hbm_kernel(Hbm
                     const uint32_t y = tbl_u32(reinterpret_cast<const uint32_t*>(p.fix), 2 * q + 1);
                     const uint32_t v = x & 0xffffu, c = x >> 16;
                     const size_t d0 = ((size_t)(p.ds_start_b >> 2) + y) * kSlots + lane;
-                    float acc = fw[(size_t)v * kSlots + lane];
-                    for (uint32_t k = 0; k < c; ++k) acc += fw[d0 + (size_t)k * kSlots];
+                    const float p0 = fw[(size_t)v * kSlots + lane];
+                    float acc = p0;
+                    for (uint32_t k = 0; k < c; ++k) acc += fw[d0 + (size_t)k * kSlots] - p0;
                     fw[(size_t)v * kSlots + lane] = acc;
                 }
                 __syncthreads();

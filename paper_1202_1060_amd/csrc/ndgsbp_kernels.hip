@@ -137,34 +137,36 @@ __device__ __forceinline__ void cn_visit(const DecodeArgs& a, const Problem& p, 
     using R = Row<M, DH>;
     const uint32_t row = (uint32_t)p.l_offset + __umul24((uint32_t)(r.cn * H) + h, (uint32_t)R::kBytes);
     float pv[DH], lo[DH], wv[DH];
-    bool real[DH], direct[DH];
+    bool real[DH];
     typename M::T st[DH];
     R::load(row, lo);
 #pragma unroll
     for (int k = 0; k < DH; ++k) {
         pv[k] = lds_f32(r.pa[k]);
         real[k] = r.pa[k] != p.pad_b;
-        direct[k] = r.ta[k] < p.ds_start_b;
     }
-    cn_core<M, DH, UNI, H>(pv, lo, real, direct, a.ymin, a.ymax, a.cmin, st, wv);
+    cn_core<M, DH, UNI, H>(pv, lo, real, a.ymin, a.ymax, a.cmin, st, wv);
 #pragma unroll
     for (int k = 0; k < DH; ++k) lds_f32(r.ta[k]) = wv[k];
     R::store(row, st);
 }
 
-// Fix-up of one VN with c edges in the group: its posterior plus its c
-// deltas, added in slot order. The first four deltas are loaded together
-// (reads past the VN's slots land in the LDS allocation and are unused).
+// Fix-up of one VN with c edges in the group: its posterior P plus the
+// change w - P of each of its edges (w: the posterior that edge alone would
+// leave, in its slot), added in slot order. The first four slots are loaded
+// together (reads past the VN's slots land in the LDS allocation and are
+// unused).
 __device__ __forceinline__ void fold_deltas(const Problem& p, uint2 e) {
     const uint32_t v = e.x & 0xffffu, c = e.x >> 16;
     const uint32_t d0 = p.ds_start_b + 4u * e.y;
-    float acc = lds_f32(4u * v);
+    const float p0 = lds_f32(4u * v);
+    float acc = p0;
     float d[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) d[k] = lds_f32(d0 + 4u * k);
 #pragma unroll
-    for (int k = 0; k < 4; ++k) acc = (uint32_t)k < c ? acc + d[k] : acc;
-    for (uint32_t k = 4; k < c; ++k) acc += lds_f32(d0 + 4u * k);
+    for (int k = 0; k < 4; ++k) acc = (uint32_t)k < c ? acc + (d[k] - p0) : acc;
+    for (uint32_t k = 4; k < c; ++k) acc += lds_f32(d0 + 4u * k) - p0;
     lds_f32(4u * v) = acc;
 }
 
