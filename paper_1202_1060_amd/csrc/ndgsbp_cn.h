@@ -41,7 +41,7 @@ __device__ __forceinline__ void cn_core(const float (&pv)[DH], const float (&lo)
         t[k] = pv[k] - lo[k];  // VN->CN message, eq. (2)
         // posteriors never hold -0.0, so the sign bit of t is the sign rule
         tb[k] = __float_as_uint(t[k]);
-        e[k] = tanh_complement(exp2_hw(-clampf(fabsf(t[k]), ymin, ymax)));
+        e[k] = eps_from_magnitude(clampf(fabsf(t[k]), ymin, ymax));
         if (!UNI) {
             e[k] = real[k] ? e[k] : 0.0f;  // 0 is the identity of (+)
             tb[k] = real[k] ? tb[k] : 0u;

@@ -38,7 +38,7 @@ struct MsgBF16 {
 // --- eq. (1) in complement-product form ---------------------------------------
 //
 // With magnitudes in log2 units (y = |x| log2 e) and v = 2^-y = e^-|x|:
-//   tanh(|x|/2) = (1 - v)/(1 + v) = 1 - eps,   eps = 2v/(1 + v),
+//   tanh(|x|/2) = (1 - v)/(1 + v) = 1 - eps,   eps = 2v/(1 + v) = 2/(1 + 2^y),
 // and eq. (1) for the edge to n reads |L_{m->n}| = 2 atanh(u) with
 // u = prod_{n' != n} (1 - eps_{n'}). The decoder never forms u: it carries
 // c = 1 - u, combining inputs with
@@ -55,14 +55,17 @@ __device__ __forceinline__ float exp2_hw(float x) { return __builtin_amdgcn_exp2
 __device__ __forceinline__ float log2_hw(float x) { return __builtin_amdgcn_logf(x); }
 __device__ __forceinline__ float rcp_hw(float x) { return __builtin_amdgcn_rcpf(x); }
 
-// eps = 1 - tanh(|x|/2) from v = 2^-y (relative error a few ulp for all y)
-__device__ __forceinline__ float tanh_complement(float v) { return 2.0f * (v * rcp_hw(1.0f + v)); }
+// eps = 1 - tanh(|x|/2) = 2v/(1 + v) = 2/(1 + 2^y) for magnitude y (log2
+// units): one exp2, one add, one reciprocal (the factor 2 folds into the
+// (+) that uses it); relative error a few ulp for all y in the clamp range
+__device__ __forceinline__ float eps_from_magnitude(float y) { return 2.0f * rcp_hw(1.0f + exp2_hw(y)); }
 
 // 1 - (1 - c)(1 - e) in one add and one fused multiply-add
 __device__ __forceinline__ float oplus(float c, float e) { return fmaf(-c, e, c + e); }
 
-// log2((2 - c)/c): the message magnitude (log2 units) for complement c
-__device__ __forceinline__ float magnitude_from_complement(float c) { return log2_hw((2.0f - c) * rcp_hw(c)); }
+// log2((2 - c)/c) = log2(2/c - 1): the message magnitude (log2 units) for
+// complement c, as one reciprocal, one fused multiply-add and one log2
+__device__ __forceinline__ float magnitude_from_complement(float c) { return log2_hw(fmaf(2.0f, rcp_hw(c), -1.0f)); }
 
 __device__ __forceinline__ float clampf(float x, float lo, float hi) { return __builtin_amdgcn_fmed3f(x, lo, hi); }
 
