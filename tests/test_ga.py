@@ -1,0 +1,58 @@
+"""GA analysis (Sec. III, Table I) on the CPU.
+
+Pins from the paper's Table I: the BP column (iterations to error-free at
+the tabulated GA threshold: 632 for the (4,6) rate-1/3 ensemble exactly,
+422 for (3,6) within one iteration) and the thresholds (1.730 dB; 1.163 dB
+within 0.001 dB). The group-shuffled columns are parity unpinned (the
+printed recursion is partly garbled): tested are the reductions (one group
+is the flooding recursion) and the ordering the paper reports
+(NDGSBP < GSBP < BP in iterations at every G).
+"""
+import math
+
+import pytest
+
+from paper_1202_1060_amd import ga
+
+
+def test_phi_closed_form_properties():
+    assert ga.phi(0.0) == 1.0
+    for xs in ([0.1, 1.0, 5.0, 9.99], [10.0, 20.0, 60.0]):  # decreasing on each piece of the fit
+        vals = [ga.phi(x) for x in xs]
+        assert all(0 < v < 1 for v in vals)
+        assert all(a > b for a, b in zip(vals, vals[1:]))
+    # the two pieces meet within 3% (the fit steps up slightly at x = 10)
+    assert abs(ga.phi(10.0 - 1e-9) / ga.phi(10.0) - 1) < 0.03
+    for x in (0.3, 3.0, 12.0, 40.0):
+        assert abs(ga.phi_inv(ga.phi(x)) - x) < 1e-9 * max(1.0, x)
+    # consistent Gaussian of mean mu: Phi(mu) = 1 - E tanh(u/2) -> 0 like
+    # sqrt(pi/mu) exp(-mu/4) for large mu
+    assert abs(ga.phi(100.0) / (math.sqrt(math.pi / 100.0) * math.exp(-25.0)) - (1 - 10 / 700)) < 1e-12
+
+
+def test_table1_bp_column():
+    assert ga.ga_bp(4, 6, 1 / 3, 1.730) == 632
+    assert abs(ga.ga_bp(3, 6, 0.5, 1.163) - 422) <= 1
+
+
+def test_table1_thresholds():
+    assert round(ga.threshold(4, 6, 1 / 3, lo=1.6, hi=1.9, steps=24), 3) == 1.730
+    assert abs(ga.threshold(3, 6, 0.5, lo=1.0, hi=1.3, steps=24) - 1.163) < 1e-3
+    # below the threshold the recursion stalls
+    assert ga.ga_bp(3, 6, 0.5, 1.10, max_iter=5000) is None
+
+
+def test_one_group_is_flooding():
+    assert ga.ga_group(3, 6, 0.5, 1.3, 1, 0.0) == ga.ga_bp(3, 6, 0.5, 1.3)
+
+
+@pytest.mark.parametrize("dv,dc,rate,eb,Gs", [(3, 6, 0.5, 1.163, (4, 12, 36)), (4, 6, 1 / 3, 1.730, (4, 16, 34))])
+def test_group_shuffled_ordering(dv, dc, rate, eb, Gs):
+    bp = ga.ga_bp(dv, dc, rate, eb)
+    last_gs = bp
+    for G in Gs:
+        gs = ga.ga_group(dv, dc, rate, eb, G, 0.0)
+        nd = ga.ga_group(dv, dc, rate, eb, G, 0.4)
+        assert nd < gs < bp, (G, nd, gs, bp)
+        assert gs <= last_gs  # more groups converge faster
+        last_gs = gs
