@@ -83,7 +83,7 @@ __global__ __launch_bounds__(HbmMaxThreads<D>::value) void ndgsbp_hbm_kernel(Hbm
     __shared__ int s_used[kSlots];    // iterations run on it
     __shared__ int s_fail[kMaxWaves][kSlots];
     __shared__ unsigned long long s_mask[3];  // [0] active, [1] to retire, [2] just filled
-    __shared__ int s_check;           // some slot checks its syndrome this iteration
+    __shared__ unsigned long long s_chk;  // slots that check their syndrome this iteration
     __shared__ int s_more;            // the launch may still have frames
 
     if (wv == 0) {
@@ -172,12 +172,14 @@ __global__ __launch_bounds__(HbmMaxThreads<D>::value) void ndgsbp_hbm_kernel(Hbm
             const int used = s_used[lane] + (act ? 1 : 0);
             s_used[lane] = used;
             const bool chk = act && (a.early_stop || used == p.max_iter);
-            const uint64_t any = __ballot(chk);
-            if (lane == 0) s_check = any != 0;
+            const uint64_t cm = __ballot(chk);
+            if (lane == 0) s_chk = cm;
         }
         __syncthreads();
-        if (s_check) {
-            // hard decision = sign bit of the posterior (no -0.0 is stored)
+        const uint64_t need = s_chk;
+        if (need) {
+            // hard decision = sign bit of the posterior (no -0.0 is stored);
+            // a wave stops once every checking slot has failed one of its checks
             uint32_t x = 0;
             for (int c = wv; c < p.m; c += nw) {
                 uint32_t par = 0;
@@ -185,6 +187,7 @@ __global__ __launch_bounds__(HbmMaxThreads<D>::value) void ndgsbp_hbm_kernel(Hbm
                 for (int k = 0; k < SD; ++k)
                     par ^= __float_as_uint(fw[(size_t)tbl_u32(p.syn_col, (uint32_t)c * SD + k) * (kSlots / 4) + lane]);
                 x |= par;
+                if ((__ballot(x >> 31) & need) == need) break;
             }
             s_fail[wv][lane] = (int)(x >> 31);
         }
@@ -194,7 +197,7 @@ __global__ __launch_bounds__(HbmMaxThreads<D>::value) void ndgsbp_hbm_kernel(Hbm
         if (wv == 0) {
             const bool act = (active >> lane) & 1ull;
             int fail = 0;
-            if (s_check)
+            if (s_chk)
                 for (int w = 0; w < nw; ++w) fail |= s_fail[w][lane];
             const int used = s_used[lane];
             const bool chk = act && (a.early_stop || used == p.max_iter);
