@@ -10,7 +10,10 @@ and syndrome flags written back to HBM).
 
 Prints one JSON line. The decoded info rate counts K = 1152 information bits
 per frame. The roofline object is for the decode kernel, bound by VALU issue
-(see the derivation of the per-edge-update slot count in the design doc).
+(26 issue slots per edge update, derived below). Further legs in the same
+line: fixed iterations, FP16 messages, the 256-problem mixed batch against
+one FP32 launch per problem, the HBM tier, and request serving with
+continuous batching (p50/p99 latency) against one FP32 launch per request.
 """
 from __future__ import annotations
 
@@ -31,7 +34,7 @@ METRIC = "decoded info Gbit/s at matched FER (served/batched vs plain); p50/p99 
 # evaluations of 1 exp + 1 log + 1 reciprocal (transcendentals issue at half
 # the full FP32 rate on gfx950, 2 slots each) plus three full-rate ops each,
 # and eight full-rate ops for the extrinsic, clamps, exclusive sum, signs and
-# add-back: 2 * (6 + 3) + 8 = 26; see the design doc.
+# add-back: 2 * (6 + 3) + 8 = 26.
 SLOTS_PER_EDGE_UPDATE = 26
 # 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz, one non-packed VALU op per lane-cycle
 PEAK_SLOTS_PER_S = 256 * 4 * 16 * 2.4e9

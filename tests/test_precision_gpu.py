@@ -9,7 +9,7 @@ import pytest
 pytestmark = pytest.mark.gpu
 
 torch = pytest.importorskip("torch")
-if not torch.cuda.is_available():  # pragma: no cover - GPU machine only
+if not torch.cuda.is_available():  # pragma: no cover - needs a GPU
     pytest.skip("needs a GPU", allow_module_level=True)
 
 import oracle  # noqa: E402
