@@ -144,6 +144,18 @@ def bench_batched(args, torch, nd, W, dev, log):
     bwall, bms = timed(lambda: batch.launch(stream), args.batch_steps)
     bstats = fer([p.out for p in probs])
     info = batch.info
+    # the same batch captured once in a graph and replayed
+    graph = torch.cuda.CUDAGraph()
+    side = torch.cuda.Stream(dev)
+    side.wait_stream(stream)
+    with torch.cuda.stream(side):
+        with torch.cuda.graph(graph, stream=side):
+            batch.launch(side)
+    stream.wait_stream(side)
+    torch.cuda.synchronize()
+    gwall, gms = timed(graph.replay, args.batch_steps)
+    gstats = fer([p.out for p in probs])
+    del graph
     batch.close()
 
     plain_out = [nd.new_outputs(p["frames"], c.n, dev, want_post=False) for p, c in zip(specs, codes)]
@@ -164,6 +176,8 @@ def bench_batched(args, torch, nd, W, dev, log):
         "batched_fp16": {"gbit_s": bits / (bms * 1e-3) / 1e9, "ms": bms, "wall_ms": bwall * 1e3,
                          "launches": info["num_launches"], "streams": info["num_streams"],
                          "options": list(opts.as_tuple()), **bstats},
+        "batched_fp16_graph_replay": {"gbit_s": bits / (gms * 1e-3) / 1e9, "ms": gms, "wall_ms": gwall * 1e3,
+                                      "frame_errors": gstats["frame_errors"]},
         "plain_fp32_per_problem": {"gbit_s": bits / (pms * 1e-3) / 1e9, "ms": pms, "wall_ms": pwall * 1e3,
                                    "launches": len(specs), **pstats},
         "speedup": pms / bms,

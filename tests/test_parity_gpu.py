@@ -308,3 +308,28 @@ def test_regrouping_every_iteration_meets_bar():
                        o["iters"].data_ptr(), 0, torch.cuda.current_stream().cuda_stream)
     assert ei.value.code == nd.LDPC_EUNSUPPORTED
     dcode.close()
+
+
+def test_degenerate_codes_and_caps():
+    """A VN in no check keeps its channel LLR; one iteration; identical
+    frames decode identically; a code with a single check of every VN."""
+    rows = [[0, 1, 2], [1, 2, 3], [2, 3, 4]]  # VN 5 is in no check
+    code = Code.from_rows(rows, 6)
+    rng = np.random.default_rng(21)
+    llr = rng.normal(1.0, 1.2, size=(1, 6)).astype(np.float32).repeat(40, axis=0)
+    dcode = nd.Code(code, windows=(2, 1, 1))
+    for it in (1, 5):
+        g, r = gpu_decode(dcode, llr, it, False), oracle.decode(code, _groups(code, (2, 1, 1)), llr, it, False)
+        assert np.all(g["post"] == g["post"][0])  # identical frames
+        np.testing.assert_allclose(g["post"][:, 5], llr[:, 5], rtol=1e-6)
+        np.testing.assert_allclose(g["post"], r["post"], rtol=1e-4, atol=1e-3)
+        assert np.all(g["iters"] == it)
+    dcode.close()
+    one = Code.from_rows([list(range(8))], 8)  # one check over all VNs
+    llr1 = rng.normal(0.5, 1.0, size=(16, 8)).astype(np.float32)
+    dcode = nd.Code(one, windows=(1, 0, 1))
+    g = gpu_decode(dcode, llr1, 3, True)
+    r = oracle.decode(one, [np.arange(1)], llr1, 3, True)
+    np.testing.assert_allclose(g["post"], r["post"], rtol=1e-4, atol=1e-3)
+    assert np.array_equal(g["iters"], r["iters"])
+    dcode.close()
