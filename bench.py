@@ -129,11 +129,15 @@ def bench_batched(args, torch, nd, W, dev, log):
         wall = (time.perf_counter() - t0) / steps
         return wall, float(np.median([a.elapsed_time(b) for a, b in evs]))
 
+    e_iter = [c.info["edge_updates"] for c in codes]
+
     def fer(outs):
         err = sum(int(np.any(o["hard"].cpu().numpy() != cw, axis=1).sum()) for o, cw in zip(outs, cws))
-        it = float(sum(int(o["iters"].sum()) for o in outs)) / frames.sum()
+        its = [int(o["iters"].sum()) for o in outs]
+        it = float(sum(its)) / frames.sum()
         lo, hi = clopper_pearson(err, int(frames.sum()))
-        return dict(fer=err / frames.sum(), frame_errors=err, ci95=[lo, hi], mean_iters=it)
+        return dict(fer=err / frames.sum(), frame_errors=err, ci95=[lo, hi], mean_iters=it,
+                    edge_updates=float(np.dot(its, e_iter)))
 
     probs = [nd.Problem(c, x, p["max_iter"], want_post=False) for c, x, p in zip(codes, llrs, specs)]
     t0 = time.perf_counter()
@@ -174,11 +178,15 @@ def bench_batched(args, torch, nd, W, dev, log):
                     "I_max 20, syndrome stop",
         "frames": int(frames.sum()), "info_bits": bits,
         "batched_fp16": {"gbit_s": bits / (bms * 1e-3) / 1e9, "ms": bms, "wall_ms": bwall * 1e3,
+                         "edge_updates_per_s": bstats["edge_updates"] / (bms * 1e-3),
+                         "roofline_frac": bstats["edge_updates"] * SLOTS_PER_EDGE_UPDATE / (bms * 1e-3)
+                         / PEAK_SLOTS_PER_S,
                          "launches": info["num_launches"], "streams": info["num_streams"],
                          "options": list(opts.as_tuple()), **bstats},
         "batched_fp16_graph_replay": {"gbit_s": bits / (gms * 1e-3) / 1e9, "ms": gms, "wall_ms": gwall * 1e3,
                                       "frame_errors": gstats["frame_errors"]},
         "plain_fp32_per_problem": {"gbit_s": bits / (pms * 1e-3) / 1e9, "ms": pms, "wall_ms": pwall * 1e3,
+                                   "edge_updates_per_s": pstats["edge_updates"] / (pms * 1e-3),
                                    "launches": len(specs), **pstats},
         "speedup": pms / bms,
     }

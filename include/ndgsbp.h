@@ -146,6 +146,10 @@ int ldpc_code_tune(ldpc_code_t code, uint32_t msg_flags, int32_t lanes_per_cn);
  * of one code run one after another on the device (each waits for the
  * previous one). Both tiers compute the same values: the HBM tier equals the
  * LDS tier with one lane per CN visit, bit for bit.
+ * Each call takes the next of 1024 work counters of the code (a ring, reset
+ * on the device by the call's last workgroup): at most 1024 decodes of one
+ * code may be executing at the same time (calls on one stream never
+ * overlap).
  * Errors: EINVAL (NULL code/llr/hard/iters, num_frames < 0, max_iter < 1,
  * bad flags), EUNSUPPORTED (no kernel variant fits the code), ENOMEM (HBM
  * workspace), EHIP. */
