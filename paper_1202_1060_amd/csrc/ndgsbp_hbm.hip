@@ -309,6 +309,7 @@ hipError_t hbm_by_degree(int D, bool uni, bool launch, const HbmArgs* a, int blo
         case 6: return hbm_by_uniform<M, 6>(uni, launch, a, blocks, threads, s, out);
         case 7: return hbm_by_uniform<M, 7>(uni, launch, a, blocks, threads, s, out);
         case 8: return hbm_by_uniform<M, 8>(uni, launch, a, blocks, threads, s, out);
+        case 10: return hbm_by_uniform<M, 10>(uni, launch, a, blocks, threads, s, out);
         case 12: return hbm_by_uniform<M, 12>(uni, launch, a, blocks, threads, s, out);
         case 16: return hbm_by_uniform<M, 16>(uni, launch, a, blocks, threads, s, out);
         case 24: return hbm_by_uniform<M, 24>(uni, launch, a, blocks, threads, s, out);

@@ -164,8 +164,8 @@ int threads_for(const ldpc_code* c, const Layout& l) {
 
 // Padded degree of the kernel variant for h lanes per CN.
 int pick_degree(int d, int h) {
-    static const int kD1[] = {4, 6, 7, 8, 12, 16, 24, 32};
-    static const int kD2[] = {4, 6, 8, 12, 16, 24, 32};
+    static const int kD1[] = {4, 6, 7, 8, 10, 12, 16, 24, 32};
+    static const int kD2[] = {4, 6, 8, 10, 12, 16, 24, 32};
     if (h == 1) {
         for (int x : kD1)
             if (d <= x) return x;

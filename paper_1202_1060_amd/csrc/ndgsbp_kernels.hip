@@ -494,6 +494,7 @@ hipError_t by_degree(int dmax, bool uni, int lanes, A... args) {
         case 6: return by_uniform<F, M, 6>(uni, lanes, args...);
         case 7: return by_uniform<F, M, 7>(uni, lanes, args...);
         case 8: return by_uniform<F, M, 8>(uni, lanes, args...);
+        case 10: return by_uniform<F, M, 10>(uni, lanes, args...);
         case 12: return by_uniform<F, M, 12>(uni, lanes, args...);
         case 16: return by_uniform<F, M, 16>(uni, lanes, args...);
         case 24: return by_uniform<F, M, 24>(uni, lanes, args...);

@@ -127,3 +127,21 @@ def test_batches_refuse_codes_beyond_lds(big):
     with pytest.raises(nd.LdpcError) as ei:
         nd.decode_batched([nd.Problem(dcode, x, 10)], msg="fp16")
     assert ei.value.code == nd.LDPC_EUNSUPPORTED
+
+
+@pytest.mark.parametrize("msg", ["fp32", "fp16"])
+def test_hbm_tier_degree_ten(msg):
+    """Degree-10 variant (checks of degree 9 and 10): the HBM tier equals
+    the one-lane LDS tier bit for bit."""
+    code = W.CODES["qc1152r2_3"]()
+    llr, _ = make_frames(code.n, 130, 2.4, 2 / 3, seed=93)
+    dcode = nd.Code(code, windows=(9, 12, 1))
+    try:
+        dcode.tune(msg, 1)
+        want = _decode(dcode, llr, 15, True, msg, hbm=False)
+        got = _decode(dcode, llr, 15, True, msg, hbm=True)
+    finally:
+        dcode.close()
+    for k in want:
+        assert np.array_equal(got[k], want[k]), k
+    print(msg, "decoded", got["syn_ok"].mean(), "mean iters", got["iters"].mean())

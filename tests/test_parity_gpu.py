@@ -333,3 +333,21 @@ def test_degenerate_codes_and_caps():
     np.testing.assert_allclose(g["post"], r["post"], rtol=1e-4, atol=1e-3)
     assert np.array_equal(g["iters"], r["iters"])
     dcode.close()
+
+
+@pytest.mark.parametrize("lanes", [1, 2])
+@pytest.mark.parametrize("which", ["qc_rate_2_3", "regular_5_10"])
+def test_degree_ten_variants(which, lanes):
+    """Checks of degree 9 and 10 (a rate-2/3 QC code: padded variant D = 10)
+    and a (5,10)-regular code (uniform D = 10), both CN-lane mappings."""
+    if which == "qc_rate_2_3":
+        code = W.CODES["qc1152r2_3"]()
+        windows = (9, 12, 1)
+        llr, _ = make_frames(code.n, 160, 2.6, 2 / 3, seed=91, encoder=W.encoder_for("qc1152r2_3"))
+    else:
+        code = regular_code(600, 5, 10, seed=77, girth6=True)
+        windows = (6, 8, 1)
+        llr, _ = make_frames(code.n, 160, 2.6, 0.5, seed=91)
+    assert int(np.diff(code.row_ptr).max()) == 10
+    g, r = _run_both(code, windows, llr, 15, True, lanes=lanes)
+    print(which, "lanes", lanes, compare(g, r))
