@@ -70,16 +70,27 @@ def make_inputs(rec, frames_per_snr):
     return np.concatenate(llrs), np.concatenate(cws)
 
 
-def cpu_baseline(code, groups, llr, rec, frames_per_snr, sample_per_snr, k_info):
+def cpu_baseline(code, groups, llr, rec, frames_per_snr, seconds, k_info):
+    """The FP64 oracle on the host cores over a bounded sample of the same
+    workload: the first F frames of every Eb/N0 point, F sized by a pilot run
+    of 16 frames per point so that the timed run takes about ``seconds``."""
     import oracle
-    idx = np.concatenate([np.arange(sample_per_snr) + i * frames_per_snr
-                          for i in range(len(rec["ebn0"]))])
+    points = len(rec["ebn0"])
+
+    def sample(per_snr):
+        return np.concatenate([np.arange(per_snr) + i * frames_per_snr for i in range(points)])
+
+    pilot = min(16, frames_per_snr)
+    t0 = time.perf_counter()
+    oracle.decode(code, groups, llr[sample(pilot)], rec["max_iter"], rec["early_stop"], nthreads=0)
+    per_snr = int(min(frames_per_snr, max(pilot, pilot * seconds / max(time.perf_counter() - t0, 1e-6))))
+    idx = sample(per_snr)
     t0 = time.perf_counter()
     out = oracle.decode(code, groups, llr[idx], rec["max_iter"], rec["early_stop"], nthreads=0)
     dt = time.perf_counter() - t0
     return dict(value=len(idx) * k_info / dt / 1e9, unit="Gbit/s", cores=int(out["threads"]),
                 kind="oracle",
-                sample=f"first {sample_per_snr} frames of each of the {len(rec['ebn0'])} Eb/N0 "
+                sample=f"first {per_snr} frames of each of the {points} Eb/N0 "
                        f"points ({len(idx)} frames), FP64, {dt:.1f} s",
                 seconds=dt)
 
@@ -345,7 +356,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--msg", default="fp32", choices=["fp32", "fp16", "bf16"])
     ap.add_argument("--frames-per-snr", type=int, default=16384)
-    ap.add_argument("--cpu-sample-per-snr", type=int, default=160)
+    ap.add_argument("--cpu-seconds", type=float, default=12.0,
+                    help="target duration of the CPU-baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fixed", action="store_true", help="skip the fixed-iteration pass")
     ap.add_argument("--no-fp16", action="store_true", help="skip the FP16-message pass")
@@ -484,7 +496,7 @@ def main():
         import oracle
         groups = oracle.windows(code.m, *rec["windows"][:2], bool(rec["windows"][2]))
         result["cpu_baseline"] = cpu_baseline(code, groups, llr_np, rec, args.frames_per_snr,
-                                              args.cpu_sample_per_snr, enc.k)
+                                              args.cpu_seconds, enc.k)
     dcode.close()
     print(json.dumps(result), flush=True)
 
