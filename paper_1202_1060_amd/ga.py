@@ -16,14 +16,21 @@ Q(sqrt(mu_total/2)), falling below 1e-6; iterations are counted from 1.
   overlap ratio r (r = 0: GSBP), following the class structure of
   eq. (4)-(17) under these readings (the printed equations are partly
   garbled): in sub-iteration g, a VN edge into the group sees its other
-  i - 1 edges as class a (CN not updated yet in this iteration: mean of the
-  previous iteration), class d (CN updated in an earlier sub-iteration of
-  this iteration: mean of those updates) or class b (CN shared with the
-  previous group, updated in sub-iteration g - 1); the fractions are those
-  of eq. (10)-(12) with g counting the groups already done (g - 1 in the
-  printed y), so that y + z never exceeds 1; the weights are the binomial
-  and trinomial mixtures of eq. (9); the iteration's CN mean is the mix of
-  eq. (17).
+  i - 1 edges as class a (CN not updated yet in this iteration), class d
+  (CN updated in an earlier sub-iteration of this iteration, outside the
+  overlap) or class b (CN shared with the previous group); the class-d
+  fraction counts the g - 1 groups already done ((g - 1)(1 - r) / (G -
+  (G - 1) r), where the printed y has g, which would let y + z exceed 1);
+  the class-d mean is the mean over the done groups with the class-b /
+  class-c proportions of eq. (5)-(6); the class-a mean is the previous
+  iteration's CN mean, taken as the average over all G groups of eq. (17)'s
+  class-b / class-c mix (the printed eq. (17) names only group G); the
+  overlap CNs' output uses the VNs with at least one class-d edge (eq. (15)
+  with p >= 1, renormalised). With r = 0 this reproduces the paper's GSBP
+  columns of Table I exactly for both ensembles (293, 262, 251 and 438,
+  386, 376); the r = 0.4 columns are not reproduced (262, 232, 223 against
+  240, 208, 196; 400, 355, 350 against 368, 324, 317), so the overlap part
+  stays a reading.
 """
 from __future__ import annotations
 
@@ -98,18 +105,41 @@ def ga_bp(dv: int, dc: int, rate: float, ebn0_db: float, pe: float = 1e-6, max_i
     return None
 
 
-def _mixture(i, p_frac, q_frac, mu_a, mu_d, mu_b, mu0):
-    """Mean VN-to-CN message of a degree-i VN whose i - 1 other edges are
-    class d with probability p_frac, class b with q_frac, else class a."""
-    tot = 0.0
+def _mixture(i, p_frac, q_frac, mu_a, mu_d, mu_b, mu0, p_min=0):
+    """Mean VN-to-CN message of a degree-i VN (eq. (4), (8), (9)) whose i - 1
+    other edges are class d with probability p_frac, class b with q_frac,
+    else class a. With p_min > 0: the mean over the VNs with at least p_min
+    class-d edges (the weights renormalised)."""
+    tot = wsum = 0.0
     a_frac = max(0.0, 1.0 - p_frac - q_frac)
     n = i - 1
-    for p in range(n + 1):
+    for p in range(p_min, n + 1):
         for q in range(n - p + 1):
             w = (math.comb(n, p) * math.comb(n - p, q) * p_frac ** p * q_frac ** q * a_frac ** (n - p - q))
             if w:
                 tot += w * (mu0 + p * mu_d + q * mu_b + (n - p - q) * mu_a)
-    return tot
+                wsum += w
+    if p_min == 0:
+        return tot
+    return tot / wsum if wsum > 0 else mu0 + n * mu_a
+
+
+def _weighted(w, mu):
+    """w * mu with a zero weight giving 0 also for an infinite mean."""
+    return w * mu if w else 0.0
+
+
+def _class_d_mean(c_means, b_means, r):
+    """Mean of the class-d messages in a sub-iteration: the groups already
+    done in this iteration, group 1 by its class-c mean and each later group
+    by its class-b and class-c means in the proportions of eq. (5) (r < 0.5)
+    or by its class-b mean (eq. (6), r >= 0.5)."""
+    if not c_means:
+        return 0.0
+    terms = [c_means[0]]
+    for b, c in zip(b_means[1:], c_means[1:]):
+        terms.append(b if r >= 0.5 else _weighted(r / (1 - r), b) + _weighted((1 - 2 * r) / (1 - r), c))
+    return sum(terms) / len(terms)
 
 
 def ga_group(dv: int, dc: int, rate: float, ebn0_db: float, G: int, r: float = 0.0, pe: float = 1e-6,
@@ -120,27 +150,25 @@ def ga_group(dv: int, dc: int, rate: float, ebn0_db: float, G: int, r: float = 0
     mu0 = channel_mean(ebn0_db, rate)
     den = G - (G - 1) * r
     z = r / den if G > 1 else 0.0
-    mu_prev = 0.0  # CN mean of the previous iteration
+    mu_prev = 0.0  # class a: the CN mean of the previous iteration
     for l in range(1, max_iter + 1):
-        done = []      # class-c means of the groups done in this iteration
-        mu_b = 0.0     # mean of the last group's overlap (class b) messages
-        mu_c_g = mu_b_g = 0.0
+        cs, bs = [], []  # class-c and class-b CN means of the groups done so far
         for g in range(1, G + 1):
-            y = (g - 1) * (1 - r) / den  # CNs updated earlier in this iteration, outside the overlap
-            zz = z if g > 1 else 0.0
-            mu_d = sum(done) / len(done) if done else 0.0
-            mv = {i: _mixture(i, y, zz, mu_prev, mu_d, mu_b, mu0) for i in lam}
-            mu_c_g = _cn_mean(mv, lam, rho)
-            if g > 1 and zz > 0:
-                # class b: the VN-to-CN messages of an overlap CN, with at
-                # least one neighbour CN updated in the previous group
-                mvb = {i: _mixture(i, y + zz, 0.0, mu_prev, mu_d if done else mu_prev, 0.0, mu0) for i in lam}
-                mu_b_g = _cn_mean(mvb, lam, rho)
+            y = (g - 1) * (1 - r) / den  # class d: CNs of earlier groups outside the overlap
+            q = z if g > 1 else 0.0      # class b: the overlap with group g - 1
+            mu_d = _class_d_mean(cs, bs, r)
+            mu_b = bs[-1] if bs else 0.0
+            c = _cn_mean({i: _mixture(i, y, q, mu_prev, mu_d, mu_b, mu0) for i in lam}, lam, rho)
+            if q > 0:
+                # the overlap CNs: VNs with at least one class-d edge
+                b = _cn_mean({i: _mixture(i, y, q, mu_prev, mu_d, mu_b, mu0, p_min=1) for i in lam}, lam, rho)
             else:
-                mu_b_g = mu_c_g
-            done.append(mu_c_g)
-            mu_b = mu_b_g
-        new = z * mu_b_g + (1.0 - z) * mu_c_g if G > 1 else mu_c_g
+                b = c
+            cs.append(c)
+            bs.append(b)
+        # the iteration's CN mean: eq. (17)'s class-b / class-c proportions,
+        # averaged over the groups of the iteration
+        new = sum(_weighted(z, b) + _weighted(1.0 - z, c) for b, c in zip(bs, cs)) / G
         if bit_error(mu0 + dv * new) < pe:
             return l
         if abs(new - mu_prev) <= 1e-14 * max(1.0, new):

@@ -2,11 +2,12 @@
 
 Pins from the paper's Table I: the BP column (iterations to error-free at
 the tabulated GA threshold: 632 for the (4,6) rate-1/3 ensemble exactly,
-422 for (3,6) within one iteration) and the thresholds (1.730 dB; 1.163 dB
-within 0.001 dB). The group-shuffled columns are parity unpinned (the
+422 for (3,6) within one iteration), the thresholds (1.730 dB; 1.163 dB
+within 0.001 dB) and the GSBP columns (r = 0) for both ensembles exactly.
+The NDGSBP columns (r = 0.4) are parity unpinned (the overlap part of the
 printed recursion is partly garbled): tested are the reductions (one group
-is the flooding recursion) and the ordering the paper reports
-(NDGSBP < GSBP < BP in iterations at every G).
+is the flooding recursion; r = 0 is GSBP) and the ordering the paper
+reports (NDGSBP < GSBP < BP in iterations at every G).
 """
 import math
 
@@ -40,6 +41,12 @@ def test_table1_thresholds():
     assert abs(ga.threshold(3, 6, 0.5, lo=1.0, hi=1.3, steps=24) - 1.163) < 1e-3
     # below the threshold the recursion stalls
     assert ga.ga_bp(3, 6, 0.5, 1.10, max_iter=5000) is None
+
+
+@pytest.mark.parametrize("dv,dc,rate,eb,Gs,want", [(3, 6, 0.5, 1.163, (4, 12, 36), (293, 262, 251)),
+                                                   (4, 6, 1 / 3, 1.730, (4, 16, 34), (438, 386, 376))])
+def test_table1_gsbp_columns(dv, dc, rate, eb, Gs, want):
+    assert tuple(ga.ga_group(dv, dc, rate, eb, G, 0.0) for G in Gs) == want
 
 
 def test_one_group_is_flooding():
