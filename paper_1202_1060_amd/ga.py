@@ -13,8 +13,8 @@ Q(sqrt(mu_total/2)), falling below 1e-6; iterations are counted from 1.
 * ``ga_bp``: the standard flooding recursion
   mu_c(l) = sum_j rho_j Phi^-1(1 - (1 - sum_i lambda_i Phi(mu0 + (i-1) mu_c(l-1)))^(j-1)).
 * ``ga_group``: a horizontal group-shuffled recursion with G groups and
-  overlap ratio r (r = 0: GSBP), following the class structure of
-  eq. (4)-(17) under these readings (the printed equations are partly
+  overlap ratio 0 <= r < 0.5 (r = 0: GSBP), following the class structure
+  of eq. (4)-(17) under these readings (the printed equations are partly
   garbled): in sub-iteration g, a VN edge into the group sees its other
   i - 1 edges as class a (CN not updated yet in this iteration), class d
   (CN updated in an earlier sub-iteration of this iteration, outside the
@@ -22,15 +22,14 @@ Q(sqrt(mu_total/2)), falling below 1e-6; iterations are counted from 1.
   fraction counts the g - 1 groups already done ((g - 1)(1 - r) / (G -
   (G - 1) r), where the printed y has g, which would let y + z exceed 1);
   the class-d mean is the mean over the done groups with the class-b /
-  class-c proportions of eq. (5)-(6); the class-a mean is the previous
-  iteration's CN mean, taken as the average over all G groups of eq. (17)'s
-  class-b / class-c mix (the printed eq. (17) names only group G); the
-  overlap CNs' output uses the VNs with at least one class-d edge (eq. (15)
-  with p >= 1, renormalised). With r = 0 this reproduces the paper's GSBP
-  columns of Table I exactly for both ensembles (293, 262, 251 and 438,
-  386, 376); the r = 0.4 columns are not reproduced (262, 232, 223 against
-  240, 208, 196; 400, 355, 350 against 368, 324, 317), so the overlap part
-  stays a reading.
+  class-c proportions of eq. (5); the overlap CNs' output uses the VNs with
+  at least one class-d edge (eq. (15) with p >= 1, renormalised); the
+  class-a mean is the mean of every CN's latest message after the previous
+  iteration (eq. (17) read as that mean: the printed form names only group
+  G). With r = 0 this reproduces the paper's GSBP columns of Table I
+  exactly for both ensembles (293, 262, 251 and 438, 386, 376); the r = 0.4
+  columns come within 1-4% (240, 211, 203 against 240, 208, 196; 373, 335,
+  331 against 368, 324, 317).
 """
 from __future__ import annotations
 
@@ -132,25 +131,42 @@ def _weighted(w, mu):
 def _class_d_mean(c_means, b_means, r):
     """Mean of the class-d messages in a sub-iteration: the groups already
     done in this iteration, group 1 by its class-c mean and each later group
-    by its class-b and class-c means in the proportions of eq. (5) (r < 0.5)
-    or by its class-b mean (eq. (6), r >= 0.5)."""
+    by its class-b and class-c means in the proportions of eq. (5)."""
     if not c_means:
         return 0.0
     terms = [c_means[0]]
     for b, c in zip(b_means[1:], c_means[1:]):
-        terms.append(b if r >= 0.5 else _weighted(r / (1 - r), b) + _weighted((1 - 2 * r) / (1 - r), c))
+        terms.append(_weighted(r / (1 - r), b) + _weighted((1 - 2 * r) / (1 - r), c))
     return sum(terms) / len(terms)
+
+
+def _latest_mean(c_means, b_means, r):
+    """Mean over all M CNs of each CN's latest message after an iteration,
+    in units of N_G CNs: group 1 keeps c_1 on the 1 - r outside the overlap
+    with group 2; a middle group keeps b_g on its overlap r and c_g on the
+    1 - 2r of its new CNs outside the next overlap; the last group keeps
+    b_G on r and c_G on 1 - r. The weights add up to G - (G - 1) r."""
+    G = len(c_means)
+    if G == 1:
+        return c_means[0]
+    num = _weighted(1 - r, c_means[0]) + _weighted(r, b_means[-1]) + _weighted(1 - r, c_means[-1])
+    for b, c in zip(b_means[1:-1], c_means[1:-1]):
+        num += _weighted(r, b) + _weighted(1 - 2 * r, c)
+    return num / (G - (G - 1) * r)
 
 
 def ga_group(dv: int, dc: int, rate: float, ebn0_db: float, G: int, r: float = 0.0, pe: float = 1e-6,
              max_iter: int = 100000):
     """Iterations of the group-shuffled GA recursion (G groups, overlap
-    ratio r; r = 0 is GSBP) until the bit error probability drops below pe."""
+    ratio 0 <= r < 0.5; r = 0 is GSBP) until the bit error probability
+    drops below pe."""
+    if not 0.0 <= r < 0.5:
+        raise ValueError("the recursion is implemented for overlap ratios 0 <= r < 0.5")
     lam, rho = _regular(dv, dc)
     mu0 = channel_mean(ebn0_db, rate)
     den = G - (G - 1) * r
     z = r / den if G > 1 else 0.0
-    mu_prev = 0.0  # class a: the CN mean of the previous iteration
+    mu_prev = 0.0  # class a: the mean CN message after the previous iteration
     for l in range(1, max_iter + 1):
         cs, bs = [], []  # class-c and class-b CN means of the groups done so far
         for g in range(1, G + 1):
@@ -166,9 +182,8 @@ def ga_group(dv: int, dc: int, rate: float, ebn0_db: float, G: int, r: float = 0
                 b = c
             cs.append(c)
             bs.append(b)
-        # the iteration's CN mean: eq. (17)'s class-b / class-c proportions,
-        # averaged over the groups of the iteration
-        new = sum(_weighted(z, b) + _weighted(1.0 - z, c) for b, c in zip(bs, cs)) / G
+        # the iteration's CN mean (eq. (17)): every CN's latest message
+        new = _latest_mean(cs, bs, r)
         if bit_error(mu0 + dv * new) < pe:
             return l
         if abs(new - mu_prev) <= 1e-14 * max(1.0, new):

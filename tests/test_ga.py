@@ -4,10 +4,11 @@ Pins from the paper's Table I: the BP column (iterations to error-free at
 the tabulated GA threshold: 632 for the (4,6) rate-1/3 ensemble exactly,
 422 for (3,6) within one iteration), the thresholds (1.730 dB; 1.163 dB
 within 0.001 dB) and the GSBP columns (r = 0) for both ensembles exactly.
-The NDGSBP columns (r = 0.4) are parity unpinned (the overlap part of the
-printed recursion is partly garbled): tested are the reductions (one group
-is the flooding recursion; r = 0 is GSBP) and the ordering the paper
-reports (NDGSBP < GSBP < BP in iterations at every G).
+The NDGSBP columns (r = 0.4) are not reproduced exactly (the overlap part
+of the printed recursion is partly garbled): they are held within 5% of
+the table; also tested are the reductions (one group is the flooding
+recursion; r = 0 is GSBP) and the ordering the paper reports
+(NDGSBP < GSBP < BP in iterations at every G).
 """
 import math
 
@@ -47,6 +48,19 @@ def test_table1_thresholds():
                                                    (4, 6, 1 / 3, 1.730, (4, 16, 34), (438, 386, 376))])
 def test_table1_gsbp_columns(dv, dc, rate, eb, Gs, want):
     assert tuple(ga.ga_group(dv, dc, rate, eb, G, 0.0) for G in Gs) == want
+
+
+@pytest.mark.parametrize("dv,dc,rate,eb,Gs,table", [(3, 6, 0.5, 1.163, (4, 12, 36), (240, 208, 196)),
+                                                    (4, 6, 1 / 3, 1.730, (4, 16, 34), (368, 324, 317))])
+def test_table1_ndgsbp_columns_within_five_percent(dv, dc, rate, eb, Gs, table):
+    for G, want in zip(Gs, table):
+        got = ga.ga_group(dv, dc, rate, eb, G, 0.4)
+        assert abs(got - want) <= 0.05 * want, (G, got, want)
+
+
+def test_overlap_ratio_range():
+    with pytest.raises(ValueError):
+        ga.ga_group(3, 6, 0.5, 1.3, 4, 0.5)
 
 
 def test_one_group_is_flooding():
