@@ -195,6 +195,95 @@ int pick_lanes(const ldpc_code* c, int max_visits, int64_t max_edges) {
     return best;
 }
 
+#ifndef NDGSBP_LDS_BANKS
+#define NDGSBP_LDS_BANKS 32
+#endif
+#ifndef NDGSBP_BANK_VISITS
+#define NDGSBP_BANK_VISITS 16
+#endif
+
+// Edge order of every CN in the two-lane mapping (order[c * D + k] = the
+// edge of CN c, by its position in the CSR row, at row position k; -1 for
+// padding). Lane h of a visit reads the posteriors at positions h*DH ..
+// h*DH + DH - 1, one per LDS instruction, so an instruction of
+// NDGSBP_BANK_VISITS consecutive visits gathers 2 x that many posteriors
+// that collide when they fall in one of the NDGSBP_LDS_BANKS banks. At its
+// first visit each CN takes the order that adds the fewest collisions with
+// the CNs already placed in that run of visits (every permutation up to
+// degree 6, else position by position). The order is kept for all of the
+// CN's visits, since its message row persists between them.
+void lane_pair_edge_order(const ldpc_h_csr* H, int n, int D, const std::vector<int32_t>& vcn,
+                          const std::vector<int32_t>& visit_ptr, std::vector<int32_t>& order) {
+    const int m = H->m, DH = D / 2, B = NDGSBP_LDS_BANKS, RUN = NDGSBP_BANK_VISITS;
+    order.assign((size_t)m * D, -1);
+    std::vector<char> placed(m, 0);
+    std::vector<int32_t> cnt((size_t)DH * B);
+    std::vector<int> perm(D), best(D);
+    auto bank = [&](int c, int q) { return q < 0 ? -1 : (int)(H->col_idx[H->row_ptr[c] + q] % B); };
+    for (size_t g = 0; g + 1 < visit_ptr.size(); ++g) {
+        for (int32_t s = visit_ptr[g]; s < visit_ptr[g + 1]; s += RUN) {
+            const int32_t e = std::min(visit_ptr[g + 1], s + RUN);
+            std::fill(cnt.begin(), cnt.end(), 0);
+            auto add = [&](int c) {
+                for (int k = 0; k < D; ++k) {
+                    const int b = bank(c, order[(size_t)c * D + k]);
+                    if (b >= 0) ++cnt[(size_t)(k % DH) * B + b];
+                }
+            };
+            for (int32_t j = s; j < e; ++j)
+                if (placed[vcn[j]]) add(vcn[j]);
+            for (int32_t j = s; j < e; ++j) {
+                const int c = vcn[j];
+                if (placed[c]) continue;
+                const int d = H->row_ptr[c + 1] - H->row_ptr[c];
+                // position k holds edge perm[k] (>= d: padding)
+                auto cost = [&](const std::vector<int>& p) {
+                    int x = 0;
+                    for (int k = 0; k < DH; ++k) {
+                        const int b0 = p[k] < d ? bank(c, p[k]) : -1, b1 = p[DH + k] < d ? bank(c, p[DH + k]) : -1;
+                        if (b0 >= 0) x += cnt[(size_t)k * B + b0];
+                        if (b1 >= 0) x += cnt[(size_t)k * B + b1];
+                        if (b0 >= 0 && b0 == b1) ++x;
+                    }
+                    return x;
+                };
+                for (int k = 0; k < D; ++k) perm[k] = k;
+                if (D <= 6) {
+                    int bc = -1;
+                    do {
+                        const int x = cost(perm);
+                        if (bc < 0 || x < bc) {
+                            bc = x;
+                            best = perm;
+                        }
+                    } while (std::next_permutation(perm.begin(), perm.end()));
+                } else {
+                    // position by position: the unused edge whose bank is least used
+                    std::vector<char> used(D, 0);
+                    for (int k = 0; k < DH; ++k)
+                        for (int h = 0; h < 2; ++h) {
+                            int pick = -1, pc = 0;
+                            for (int q = 0; q < D; ++q) {
+                                if (used[q]) continue;
+                                const int b = q < d ? bank(c, q) : -1;
+                                const int x = b < 0 ? 0 : cnt[(size_t)k * B + b];
+                                if (pick < 0 || x < pc) {
+                                    pick = q;
+                                    pc = x;
+                                }
+                            }
+                            used[pick] = 1;
+                            best[h * DH + k] = pick;
+                        }
+                }
+                for (int k = 0; k < D; ++k) order[(size_t)c * D + k] = best[k] < d ? best[k] : -1;
+                placed[c] = 1;
+                add(c);
+            }
+        }
+    }
+}
+
 MsgKind msg_kind(uint32_t flags) {
     return (flags & LDPC_FLAG_MSG_FP16) ? kMsgF16 : (flags & LDPC_FLAG_MSG_BF16) ? kMsgBF16 : kMsgF32;
 }
@@ -724,6 +813,11 @@ int ldpc_code_create(const ldpc_h_csr* H, const ldpc_grouping* grouping, int32_t
 
     // per-mapping tables: edge half-records padded to D, syndrome rows
     std::vector<uint32_t> vw_h[2], syn_h[2];
+    std::vector<int32_t> order2;  // two-lane mapping: row position -> edge of the CN
+    {
+        const int D2 = pick_degree(std::max(1, maxd), 2);
+        if (D2 > 0) lane_pair_edge_order(H, n, D2, vcn, visit_ptr, order2);
+    }
     for (int h = 1; h <= 2; ++h) {
         Layout& l = c->lay[h - 1];
         const int D = pick_degree(std::max(1, maxd), h);
@@ -742,9 +836,10 @@ int ldpc_code_create(const ldpc_h_csr* H, const ldpc_grouping* grouping, int32_t
             const int32_t e0 = vdeg_of[j], d = vdeg_of[j + 1] - e0;
             for (int k = 0; k < D; ++k) {
                 uint32_t src = 4u * (uint32_t)n, dst = 4u * (uint32_t)n;  // padding edge
-                if (k < d) {
-                    src = 4u * esrc[e0 + k];
-                    dst = 4u * edst[e0 + k];
+                const int32_t q = h == 2 ? order2[(size_t)vcn[j] * D + k] : (k < d ? k : -1);
+                if (q >= 0) {
+                    src = 4u * esrc[e0 + q];
+                    dst = 4u * edst[e0 + q];
                 }
                 const size_t half = (j * h + (size_t)(k / DH)) * W;
                 vw[half + k % DH] = src;

