@@ -202,32 +202,33 @@ int pick_lanes(const ldpc_code* c, int max_visits, int64_t max_edges) {
 #define NDGSBP_BANK_VISITS 16
 #endif
 
-// Edge order of every CN in the two-lane mapping (order[c * D + k] = the
-// edge of CN c, by its position in the CSR row, at row position k; -1 for
-// padding). Lane h of a visit reads the posteriors at positions h*DH ..
-// h*DH + DH - 1, one per LDS instruction, so an instruction of
-// NDGSBP_BANK_VISITS consecutive visits gathers 2 x that many posteriors
-// that collide when they fall in one of the NDGSBP_LDS_BANKS banks. At its
-// first visit each CN takes the order that adds the fewest collisions with
-// the CNs already placed in that run of visits (every permutation up to
-// degree 6, else position by position). The order is kept for all of the
-// CN's visits, since its message row persists between them.
-void lane_pair_edge_order(const ldpc_h_csr* H, int n, int D, const std::vector<int32_t>& vcn,
-                          const std::vector<int32_t>& visit_ptr, std::vector<int32_t>& order) {
-    const int m = H->m, DH = D / 2, B = NDGSBP_LDS_BANKS, RUN = NDGSBP_BANK_VISITS;
+// Edge order of every CN in the mapping with `lanes` lanes per CN visit
+// (order[c * D + k] = the edge of CN c, by its position in the CSR row, at
+// row position k; -1 for padding). Lane h of a visit reads the posteriors
+// at positions h*DH .. h*DH + DH - 1, one per LDS instruction, so one
+// instruction of a run of 32 lanes (32 / lanes consecutive visits) gathers
+// 32 posteriors, which collide when they fall in one of the
+// NDGSBP_LDS_BANKS banks. At its first visit each CN takes the order that
+// adds the fewest collisions with the CNs already placed in its run (every
+// permutation up to degree 6, else position by position). The order is
+// kept for all of the CN's visits, since its message row persists between
+// them; it changes results only by the rounding order of eq. (1).
+void edge_order(const ldpc_h_csr* H, int lanes, int D, const std::vector<int32_t>& vcn,
+                const std::vector<int32_t>& visit_ptr, std::vector<int32_t>& order) {
+    const int m = H->m, DH = D / lanes, B = NDGSBP_LDS_BANKS, RUN = 32 / lanes;
     order.assign((size_t)m * D, -1);
     std::vector<char> placed(m, 0);
     std::vector<int32_t> cnt((size_t)DH * B);
     std::vector<int> perm(D), best(D);
-    auto bank = [&](int c, int q) { return q < 0 ? -1 : (int)(H->col_idx[H->row_ptr[c] + q] % B); };
+    auto bank = [&](int c, int q) { return (int)(H->col_idx[H->row_ptr[c] + q] % B); };
     for (size_t g = 0; g + 1 < visit_ptr.size(); ++g) {
         for (int32_t s = visit_ptr[g]; s < visit_ptr[g + 1]; s += RUN) {
             const int32_t e = std::min(visit_ptr[g + 1], s + RUN);
             std::fill(cnt.begin(), cnt.end(), 0);
             auto add = [&](int c) {
                 for (int k = 0; k < D; ++k) {
-                    const int b = bank(c, order[(size_t)c * D + k]);
-                    if (b >= 0) ++cnt[(size_t)(k % DH) * B + b];
+                    const int q = order[(size_t)c * D + k];
+                    if (q >= 0) ++cnt[(size_t)(k % DH) * B + bank(c, q)];
                 }
             };
             for (int32_t j = s; j < e; ++j)
@@ -236,15 +237,20 @@ void lane_pair_edge_order(const ldpc_h_csr* H, int n, int D, const std::vector<i
                 const int c = vcn[j];
                 if (placed[c]) continue;
                 const int d = H->row_ptr[c + 1] - H->row_ptr[c];
-                // position k holds edge perm[k] (>= d: padding)
+                // position k holds edge perm[k] (>= d: padding, one shared word)
                 auto cost = [&](const std::vector<int>& p) {
                     int x = 0;
-                    for (int k = 0; k < DH; ++k) {
-                        const int b0 = p[k] < d ? bank(c, p[k]) : -1, b1 = p[DH + k] < d ? bank(c, p[DH + k]) : -1;
-                        if (b0 >= 0) x += cnt[(size_t)k * B + b0];
-                        if (b1 >= 0) x += cnt[(size_t)k * B + b1];
-                        if (b0 >= 0 && b0 == b1) ++x;
-                    }
+                    for (int k = 0; k < DH; ++k)
+                        for (int h = 0; h < lanes; ++h) {
+                            const int q = p[h * DH + k];
+                            if (q >= d) continue;
+                            const int b = bank(c, q);
+                            x += cnt[(size_t)k * B + b];
+                            for (int h2 = 0; h2 < h; ++h2) {
+                                const int q2 = p[h2 * DH + k];
+                                if (q2 < d && bank(c, q2) == b) ++x;
+                            }
+                        }
                     return x;
                 };
                 for (int k = 0; k < D; ++k) perm[k] = k;
@@ -260,19 +266,20 @@ void lane_pair_edge_order(const ldpc_h_csr* H, int n, int D, const std::vector<i
                 } else {
                     // position by position: the unused edge whose bank is least used
                     std::vector<char> used(D, 0);
+                    std::vector<int32_t> local((size_t)DH * B, 0);
                     for (int k = 0; k < DH; ++k)
-                        for (int h = 0; h < 2; ++h) {
+                        for (int h = 0; h < lanes; ++h) {
                             int pick = -1, pc = 0;
                             for (int q = 0; q < D; ++q) {
                                 if (used[q]) continue;
-                                const int b = q < d ? bank(c, q) : -1;
-                                const int x = b < 0 ? 0 : cnt[(size_t)k * B + b];
+                                const int x = q < d ? cnt[(size_t)k * B + bank(c, q)] + local[(size_t)k * B + bank(c, q)] : 0;
                                 if (pick < 0 || x < pc) {
                                     pick = q;
                                     pc = x;
                                 }
                             }
                             used[pick] = 1;
+                            if (pick < d) ++local[(size_t)k * B + bank(c, pick)];
                             best[h * DH + k] = pick;
                         }
                 }
@@ -813,11 +820,7 @@ int ldpc_code_create(const ldpc_h_csr* H, const ldpc_grouping* grouping, int32_t
 
     // per-mapping tables: edge half-records padded to D, syndrome rows
     std::vector<uint32_t> vw_h[2], syn_h[2];
-    std::vector<int32_t> order2;  // two-lane mapping: row position -> edge of the CN
-    {
-        const int D2 = pick_degree(std::max(1, maxd), 2);
-        if (D2 > 0) lane_pair_edge_order(H, n, D2, vcn, visit_ptr, order2);
-    }
+    std::vector<int32_t> order_h[2];  // per mapping: row position -> edge of the CN
     for (int h = 1; h <= 2; ++h) {
         Layout& l = c->lay[h - 1];
         const int D = pick_degree(std::max(1, maxd), h);
@@ -830,13 +833,15 @@ int ldpc_code_create(const ldpc_h_csr* H, const ldpc_grouping* grouping, int32_t
             if (H->row_ptr[i + 1] - H->row_ptr[i] != D) l.uniform = false;
         const int DH = D / h;
         const int W = (2 * DH + 3) / 4 * 4;  // words per half-record
+        std::vector<int32_t>& order = order_h[h - 1];
+        edge_order(H, h, D, vcn, visit_ptr, order);
         std::vector<uint32_t>& vw = vw_h[h - 1];
         vw.assign(vcn.size() * (size_t)h * W, 0u);
         for (size_t j = 0; j < vcn.size(); ++j) {
             const int32_t e0 = vdeg_of[j], d = vdeg_of[j + 1] - e0;
             for (int k = 0; k < D; ++k) {
                 uint32_t src = 4u * (uint32_t)n, dst = 4u * (uint32_t)n;  // padding edge
-                const int32_t q = h == 2 ? order2[(size_t)vcn[j] * D + k] : (k < d ? k : -1);
+                const int32_t q = order[(size_t)vcn[j] * D + k];
                 if (q >= 0) {
                     src = 4u * esrc[e0 + q];
                     dst = 4u * edst[e0 + q];
@@ -849,9 +854,31 @@ int ldpc_code_create(const ldpc_h_csr* H, const ldpc_grouping* grouping, int32_t
         const int SD = (D + 3) / 4 * 4;  // syndrome row stride
         std::vector<uint32_t>& syn = syn_h[h - 1];
         syn.assign((size_t)m * SD, 4u * (uint32_t)(n + 1));
-        for (int i = 0; i < m; ++i)
-            for (int32_t q = H->row_ptr[i]; q < H->row_ptr[i + 1]; ++q)
-                syn[(size_t)i * SD + (q - H->row_ptr[i])] = 4u * (uint32_t)H->col_idx[q];
+        // A check's entries may sit in any order (its parity is a XOR). Lane
+        // t checks c = t (+ multiples of the workgroup size), one entry per
+        // LDS instruction, so 32 consecutive checks are read together: each
+        // check of such a run puts its VNs at the free positions whose bank
+        // is least used in the run so far (padding reads one shared word).
+        {
+            const int B = NDGSBP_LDS_BANKS;
+            std::vector<int32_t> used((size_t)SD * B);
+            for (int r0 = 0; r0 < m; r0 += 32) {
+                std::fill(used.begin(), used.end(), 0);
+                for (int i = r0; i < std::min(m, r0 + 32); ++i) {
+                    uint32_t* row = &syn[(size_t)i * SD];
+                    std::vector<char> taken(SD, 0);
+                    for (int32_t q = H->row_ptr[i]; q < H->row_ptr[i + 1]; ++q) {
+                        const int b = H->col_idx[q] % B;
+                        int pick = -1;
+                        for (int k = 0; k < SD; ++k)
+                            if (!taken[k] && (pick < 0 || used[(size_t)k * B + b] < used[(size_t)pick * B + b])) pick = k;
+                        taken[pick] = 1;
+                        ++used[(size_t)pick * B + b];
+                        row[pick] = 4u * (uint32_t)H->col_idx[q];
+                    }
+                }
+            }
+        }
     }
     // FP32 messages: the slot-count choice. 16-bit messages: one lane per
     // visit, which measured faster than two on the (3,6)-regular n=2304
