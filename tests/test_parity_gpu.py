@@ -351,3 +351,19 @@ def test_degree_ten_variants(which, lanes):
     assert int(np.diff(code.row_ptr).max()) == 10
     g, r = _run_both(code, windows, llr, 15, True, lanes=lanes)
     print(which, "lanes", lanes, compare(g, r))
+
+
+@pytest.mark.parametrize("lanes", [1, 2])
+@pytest.mark.parametrize("dv,dc,n", [(2, 4, 96), (3, 7, 336), (3, 8, 256), (3, 12, 384), (3, 16, 512),
+                                     (4, 24, 480), (4, 32, 512)])
+def test_every_uniform_degree_variant(dv, dc, n, lanes):
+    """Each padded-degree kernel variant on a regular code whose checks all
+    have that degree (the uniform form; degree 7 with two lanes runs the
+    degree-8 variant with one padding edge per check), both CN-lane
+    mappings."""
+    code = regular_code(n, dv, dc, seed=3, girth6=False)
+    rate = 1.0 - dv / dc
+    llr, _ = make_frames(code.n, 64, 3.0 if dc <= 12 else 4.5, rate, seed=95)
+    windows = (4, max(1, code.m // 16), 1)
+    g, r = _run_both(code, windows, llr, 12, True, lanes=lanes)
+    print((dv, dc, n), "lanes", lanes, compare(g, r))
