@@ -154,7 +154,11 @@ def bench_batched(args, torch, nd, W, dev, log):
     t0 = time.perf_counter()
     opts = autotune.tune_batch(probs, msg=rec["msg"], early_stop=rec["early_stop"],
                                cache=args.tune_cache)
-    log(f"batched options {opts} ({time.perf_counter() - t0:.1f} s)")
+    lane_use = {}
+    for p in probs:
+        lane_use[p.code.info["lanes_fp16"]] = lane_use.get(p.code.info["lanes_fp16"], 0) + 1
+    log(f"batched options {opts}, problems per CN-lane mapping {dict(sorted(lane_use.items()))} "
+        f"({time.perf_counter() - t0:.1f} s)")
     batch = nd.Batch(probs, msg=rec["msg"], early_stop=rec["early_stop"], options=opts)
     bwall, bms = timed(lambda: batch.launch(stream), args.batch_steps)
     bstats = fer([p.out for p in probs])
@@ -193,7 +197,9 @@ def bench_batched(args, torch, nd, W, dev, log):
                          "roofline_frac": bstats["edge_updates"] * SLOTS_PER_EDGE_UPDATE / (bms * 1e-3)
                          / PEAK_SLOTS_PER_S,
                          "launches": info["num_launches"], "streams": info["num_streams"],
-                         "options": list(opts.as_tuple()), **bstats},
+                         "options": list(opts.as_tuple()),
+                         "problems_per_lane_mapping": {str(k): v for k, v in sorted(lane_use.items())},
+                         **bstats},
         "batched_fp16_graph_replay": {"gbit_s": bits / (gms * 1e-3) / 1e9, "ms": gms, "wall_ms": gwall * 1e3,
                                       "frame_errors": gstats["frame_errors"]},
         "plain_fp32_per_problem": {"gbit_s": bits / (pms * 1e-3) / 1e9, "ms": pms, "wall_ms": pwall * 1e3,

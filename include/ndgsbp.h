@@ -118,8 +118,9 @@ int ldpc_code_query(ldpc_code_t code, ldpc_code_info* info);
 
 /* Choose the CN-phase mapping of later decodes of `code` with the message
  * format in msg_flags (0, LDPC_FLAG_MSG_FP16 or LDPC_FLAG_MSG_BF16): one lane
- * per CN visit (1) or two lanes sharing it (2); 0 restores the built-in
- * choice. For tuners: the mappings compute eq. (1) with the same operations
+ * per CN visit (1), or two or four lanes sharing it (2, 4; the padded degree
+ * is then a multiple of the lane count); 0 restores the built-in choice
+ * (never 4). For tuners: the mappings compute eq. (1) with the same operations
  * in a different summation order, so results agree up to float rounding.
  * Not synchronised with decodes in flight on other threads.
  * Errors: EINVAL (bad flags or value), EUNSUPPORTED (no kernel variant
@@ -185,7 +186,8 @@ typedef struct {
 /* Launch choices of a batch (the autotuner's knobs). */
 typedef struct {
     int32_t lanes_per_cn;  /* 0: each code's mapping for the message format
-                              (ldpc_code_tune); 1 or 2: that mapping for all */
+                              (ldpc_code_tune); 1, 2 or 4: that mapping for
+                              all                                           */
     int32_t split_by_size; /* nonzero: one launch per power-of-two LDS size
                               within a kernel variant (workgroups sized for
                               their problems); 0: one launch per variant    */

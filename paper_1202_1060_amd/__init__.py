@@ -108,7 +108,7 @@ class Code:
         self.device = device
 
     def tune(self, msg: str, lanes_per_cn: int) -> None:
-        """Pick the CN-phase mapping (1 or 2 lanes per CN visit, 0 = default)
+        """Pick the CN-phase mapping (1, 2 or 4 lanes per CN visit, 0 = default)
         used by decodes with message format ``msg``."""
         ldpc_code_tune(self.handle, msg_flag(msg), lanes_per_cn)
         self.info = ldpc_code_query(self.handle)

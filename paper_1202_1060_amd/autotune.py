@@ -3,8 +3,9 @@
 It times candidate launch choices on the caller's own problems (HIP events
 on one stream, after a warm-up launch) and keeps the fastest. The choices:
 
-* CN-lane mapping: one lane per CN visit, or two lanes sharing it
-  (``lanes_per_cn``), or each code's own choice;
+* CN-lane mapping: one lane per CN visit, or two or four lanes sharing it
+  (``lanes_per_cn``), or each code's own choice, which the tuner first sets
+  per code and grouping by timing it alone (``tune_lanes_per_code``);
 * launch classes: one persistent launch per kernel variant, or one per
   variant and power-of-two LDS size (``split_by_size``), which sizes each
   launch's workgroups and LDS to its problems;
@@ -88,18 +89,70 @@ def _time_launches(fn, reps, stream):
     return ts[len(ts) // 2]
 
 
+def tune_lanes_per_code(problems, *, msg: str = "fp16", early_stop: bool = True, reps: int = 3,
+                        min_frames: int = 8192, log=None):
+    """For each set of problems that share a code and grouping: time that
+    set alone (its frames repeated up to about ``min_frames``, so that the
+    launch runs in steady state rather than in its tail) with 1, 2 and 4
+    lanes per CN visit, and tune the set's codes (ldpc_code_tune) to the
+    fastest. Returns {code signature: lanes}."""
+    sets = {}
+    for p in problems:
+        sets.setdefault(_code_sig(p.code), []).append(p)
+    dev = problems[0].llr.device
+    stream = torch.cuda.current_stream(dev)
+    chosen = {}
+    for sig, ps in sets.items():
+        frames = sum(int(p.llr.shape[0]) for p in ps)
+        if frames == 0:
+            continue
+        rep = max(1, -(-min_frames // frames))
+        llr = torch.cat([p.llr for p in ps] * rep)
+        code = ps[0].code
+        best = None
+        for lanes in (1, 2, 4):
+            try:
+                code.tune(msg, lanes)
+            except Exception:  # no kernel variant with that mapping
+                continue
+            b = Batch([Problem(code, llr, max(p.max_iter for p in ps), want_post=False)], msg=msg,
+                      early_stop=early_stop, options=BatchOptions(0, 1, 512, 1))
+            ms = _time_launches(lambda: b.launch(stream), reps, stream)
+            b.close()
+            if best is None or ms < best[0]:
+                best = (ms, lanes)
+        for p in ps:
+            p.code.tune(msg, best[1])
+        chosen[sig] = best[1]
+        if log:
+            log(f"autotune lanes {sig[:2]} x{len(ps)}: {best[1]} ({best[0]:.3f} ms)")
+    return chosen
+
+
 def tune_batch(problems, *, msg: str = "fp16", early_stop: bool = True, reps: int = 3,
-               cache: str | None = None, candidates=None, force: bool = False, log=None):
-    """Fastest BatchOptions for these problems (cached). Candidates that a
-    code cannot take (e.g. two lanes where its variant has none) are
+               cache: str | None = None, candidates=None, force: bool = False, per_code_lanes: bool = True,
+               log=None):
+    """Fastest BatchOptions for these problems (cached). With
+    ``per_code_lanes`` the codes are first tuned set by set
+    (tune_lanes_per_code), which the candidates with lanes_per_cn = 0 use;
+    the codes keep those mappings only if such a candidate wins. Candidates
+    that a code cannot take (e.g. two lanes where its variant has none) are
     skipped."""
     path = _cache_path(cache)
     key = batch_signature(problems, msg, early_stop)
     db = _load(path)
     if not force and key in db:
+        lanes = {tuple(k): v for k, v in db[key].get("code_lanes", [])}
+        for p in problems:
+            if _code_sig(p.code) in lanes:
+                p.code.tune(msg, lanes[_code_sig(p.code)])
         return BatchOptions.from_tuple(db[key]["options"])
     dev = problems[0].llr.device
     stream = torch.cuda.current_stream(dev)
+    field = "lanes_" + msg
+    before = [p.code.info[field] for p in problems]
+    chosen = tune_lanes_per_code(problems, msg=msg, early_stop=early_stop, reps=reps, log=log) \
+        if per_code_lanes else {}
     results = []
     for opt in (candidates or batch_candidates()):
         try:
@@ -116,8 +169,14 @@ def tune_batch(problems, *, msg: str = "fp16", early_stop: bool = True, reps: in
     if not results:
         raise RuntimeError("no launch option worked for this batch")
     ms, best = min(results, key=lambda r: r[0])
+    if best.lanes_per_cn != 0 and chosen:
+        # the per-code mappings lost: give the codes back their own
+        for p, lanes in zip(problems, before):
+            p.code.tune(msg, lanes)
+        chosen = {}
     db = _load(path)
-    db[key] = dict(options=list(best.as_tuple()), ms=ms, tried=len(results), when=time.time())
+    db[key] = dict(options=list(best.as_tuple()), ms=ms, tried=len(results), when=time.time(),
+                   code_lanes=[[list(k), v] for k, v in chosen.items()])
     _store(path, db)
     return best
 
@@ -138,7 +197,7 @@ def tune_code(code: Code, llr: torch.Tensor, max_iter: int, *, msg: str = "fp32"
     stream = torch.cuda.current_stream(llr.device)
     out = new_outputs(int(llr.shape[0]), code.n, llr.device, want_post=False)
     best = None
-    for lanes in (1, 2):
+    for lanes in (1, 2, 4):
         try:
             code.tune(msg, lanes)
         except Exception:
@@ -156,4 +215,5 @@ def tune_code(code: Code, llr: torch.Tensor, max_iter: int, *, msg: str = "fp32"
     return best[1]
 
 
-__all__ = ["tune_batch", "tune_code", "batch_signature", "batch_candidates", "Problem"]
+__all__ = ["tune_batch", "tune_code", "tune_lanes_per_code", "batch_signature", "batch_candidates",
+           "Problem"]

@@ -14,9 +14,14 @@ namespace dev {
 __device__ __forceinline__ uint32_t pair_swap(uint32_t x) {
     return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0xB1, 0xF, 0xF, false);  // quad_perm [1,0,3,2]
 }
+// Value of the lane two places away within a quad (lanes 4i..4i+3), by DPP.
+__device__ __forceinline__ uint32_t quad_half_swap(uint32_t x) {
+    return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x4E, 0xF, 0xF, false);  // quad_perm [2,3,0,1]
+}
 
 // One lane's DH edges of a CN visit (H lanes per CN; with H = 2 the lanes of
-// a pair hold the two halves of the row).
+// a pair hold the two halves of the row, with H = 4 the lanes of a quad its
+// four quarters).
 //   pv[k]     posterior of edge k's VN (log2 units; never -0.0)
 //   lo[k]     the edge's old CN->VN message (as stored, widened)
 //   real[k]   edge k is not padding (ignored when UNI)
@@ -24,9 +29,10 @@ __device__ __forceinline__ uint32_t pair_swap(uint32_t x) {
 // posterior being the total of eq. (3)) and eps = 1 - tanh(|t|/2); the eps of
 // the other edges of the CN are combined with (+) (ndgsbp_math.h) by exclusive
 // prefix and suffix; with H = 2 the two lanes exchange their partial
-// combinations and sign parities by DPP. Outputs: st[k] the new message in
-// the storage format, wv[k] = new + t, the VN's posterior as this edge alone
-// would leave it. A VN with no other edge in the group takes wv as its
+// combinations and sign parities by DPP; with H = 4 a lane combines its
+// pair partner's partial with the other pair's total (two DPP steps).
+// Outputs: st[k] the new message in the storage format, wv[k] = new + t,
+// the VN's posterior as this edge alone would leave it. A VN with no other edge in the group takes wv as its
 // posterior; for a VN with several, wv - pv is this edge's change (new - old
 // up to rounding) and the fix-up adds the changes of all its edges.
 template <class M, int DH, bool UNI, int H>
@@ -58,6 +64,14 @@ __device__ __forceinline__ void cn_core(const float (&pv)[DH], const float (&lo)
         const float mine = DH > 1 ? oplus(pre[DH - 1], e[DH - 1]) : e[0];
         suf = __uint_as_float(pair_swap(__float_as_uint(mine)));
         sall ^= pair_swap(sall);
+        c[DH - 1] = DH > 1 ? oplus(pre[DH - 1], suf) : suf;
+    } else if (H == 4) {
+        const float mine = DH > 1 ? oplus(pre[DH - 1], e[DH - 1]) : e[0];
+        const float partner = __uint_as_float(pair_swap(__float_as_uint(mine)));
+        const float other_pair = __uint_as_float(quad_half_swap(__float_as_uint(oplus(mine, partner))));
+        suf = oplus(partner, other_pair);
+        sall ^= pair_swap(sall);
+        sall ^= quad_half_swap(sall);
         c[DH - 1] = DH > 1 ? oplus(pre[DH - 1], suf) : suf;
     } else {
         suf = 0.0f;

@@ -45,7 +45,7 @@ struct ldpc_code {
     int32_t max_vn_degree;
     int32_t max_group_visits;
     int32_t max_slots;
-    ndgsbp::Layout lay[2];    // lay[H - 1]: tables for H lanes per CN visit
+    ndgsbp::Layout lay[4];    // lay[H - 1]: tables for H = 1, 2 or 4 lanes per CN visit
     int32_t lanes_for[3];     // chosen H per message format (MsgKind)
     int32_t lanes_default[3];
     size_t max_lds;   // LDS a workgroup may use on the code's device

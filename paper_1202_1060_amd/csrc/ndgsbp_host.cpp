@@ -162,19 +162,16 @@ int threads_for(const ldpc_code* c, const Layout& l) {
     return std::max(64, std::min(t, cap));
 }
 
-// Padded degree of the kernel variant for h lanes per CN.
+// Padded degree of the kernel variant for h lanes per CN (a multiple of h).
 int pick_degree(int d, int h) {
-    static const int kD1[] = {4, 6, 7, 8, 10, 12, 16, 24, 32};
-    static const int kD2[] = {4, 6, 8, 10, 12, 16, 24, 32};
-    if (h == 1) {
-        for (int x : kD1)
-            if (d <= x) return x;
-    } else {
-        for (int x : kD2)
-            if (d <= x) return x;
-    }
+    static const int kD[] = {4, 6, 7, 8, 10, 12, 16, 24, 32};
+    for (int x : kD)
+        if (d <= x && x % h == 0) return x;
     return -1;
 }
+
+// Lanes per CN visit that a mapping may use.
+bool valid_lanes(int h) { return h == 1 || h == 2 || h == 4; }
 
 // Lanes per CN visit for a message format: the mapping that wastes the fewest
 // lane-edge slots in the CN phase (idle lanes of the last wave plus padding
@@ -427,7 +424,8 @@ void free_batch(ldpc_batch* b) {
 }
 
 int check_options(const ldpc_batch_options& o) {
-    if (o.lanes_per_cn < 0 || o.lanes_per_cn > 2) return fail(LDPC_EINVAL, "lanes_per_cn must be 0, 1 or 2");
+    if (o.lanes_per_cn != 0 && !valid_lanes(o.lanes_per_cn))
+        return fail(LDPC_EINVAL, "lanes_per_cn must be 0, 1, 2 or 4");
     if (o.max_threads < 0 || o.max_threads % 64 || o.max_threads > 1024)
         return fail(LDPC_EINVAL, "max_threads must be 0 or a multiple of 64 up to 1024");
     if (o.streams < 0 || o.streams > kMaxBatchStreams) return fail(LDPC_EINVAL, "streams must be in 0..8");
@@ -819,9 +817,9 @@ int ldpc_code_create(const ldpc_h_csr* H, const ldpc_grouping* grouping, int32_t
     }
 
     // per-mapping tables: edge half-records padded to D, syndrome rows
-    std::vector<uint32_t> vw_h[2], syn_h[2];
-    std::vector<int32_t> order_h[2];  // per mapping: row position -> edge of the CN
-    for (int h = 1; h <= 2; ++h) {
+    std::vector<uint32_t> vw_h[4], syn_h[4];
+    std::vector<int32_t> order_h[4];  // per mapping: row position -> edge of the CN
+    for (int h : {1, 2, 4}) {
         Layout& l = c->lay[h - 1];
         const int D = pick_degree(std::max(1, maxd), h);
         if (D < 0 || D % h) continue;
@@ -910,7 +908,8 @@ int ldpc_code_create(const ldpc_h_csr* H, const ldpc_grouping* grouping, int32_t
     if (e == hipSuccess) e = upload(&c->dev.visit_ptr, visit_ptr);
     if (e == hipSuccess) e = upload(&c->dev.fix, fix);
     if (e == hipSuccess) e = upload(&c->dev.fix_ptr, fix_ptr);
-    for (int h = 1; h <= 2 && e == hipSuccess; ++h) {
+    for (int h : {1, 2, 4}) {
+        if (e != hipSuccess) break;
         if (!c->lay[h - 1].valid) continue;
         e = upload(&c->lay[h - 1].vw, vw_h[h - 1]);
         if (e == hipSuccess) e = upload(&c->lay[h - 1].syn_col, syn_h[h - 1]);
@@ -977,7 +976,7 @@ int ldpc_code_tune(ldpc_code_t c, uint32_t msg_flags, int32_t lanes_per_cn) {
         c->lanes_for[kind] = c->lanes_default[kind];
         return LDPC_OK;
     }
-    if (lanes_per_cn != 1 && lanes_per_cn != 2) return fail(LDPC_EINVAL, "lanes_per_cn must be 0, 1 or 2");
+    if (!valid_lanes(lanes_per_cn)) return fail(LDPC_EINVAL, "lanes_per_cn must be 0, 1, 2 or 4");
     if (!c->lay[lanes_per_cn - 1].valid) return fail(LDPC_EUNSUPPORTED, "no kernel variant with that mapping");
     c->lanes_for[kind] = lanes_per_cn;
     return LDPC_OK;

@@ -178,7 +178,7 @@ __device__ __forceinline__ void fold_deltas(const Problem& p, uint2 e) {
 // workgroups resident per CU.
 template <int SD, int H>
 struct SynChecks {
-    static constexpr int value = SD > 8 ? 0 : H == 2 ? 1 : 2;
+    static constexpr int value = SD > 8 ? 0 : H >= 2 ? 1 : 2;
 };
 template <int SD, int K>
 struct SynRows {
@@ -478,6 +478,9 @@ hipError_t by_lanes(int lanes, A... args) {
     if (lanes == 1) return F<M, D, UNI, 1>::run(args...);
     if constexpr (D % 2 == 0) {
         if (lanes == 2) return F<M, D, UNI, 2>::run(args...);
+    }
+    if constexpr (D % 4 == 0) {
+        if (lanes == 4) return F<M, D, UNI, 4>::run(args...);
     }
     return hipErrorInvalidValue;
 }

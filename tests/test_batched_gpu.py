@@ -73,7 +73,7 @@ def _single(s, i, msg, early_stop=True):
 
 
 @pytest.mark.parametrize("msg", ["fp16", "fp32", "bf16"])
-@pytest.mark.parametrize("opts", [(0, 1, 0, 4), (0, 0, 0, 1), (1, 1, 128, 2), (2, 0, 256, 8)])
+@pytest.mark.parametrize("opts", [(0, 1, 0, 4), (0, 0, 0, 1), (1, 1, 128, 2), (2, 0, 256, 8), (4, 1, 512, 4)])
 def test_batch_equals_single_decodes(mixed, msg, opts):
     o = nd.BatchOptions.from_tuple(opts)
     lanes = o.lanes_per_cn
@@ -201,13 +201,23 @@ def test_autotuner_picks_and_caches(mixed, tmp_path):
     probs = mixed.problems()
     cache = str(tmp_path / "tune.json")
     cands = [nd.BatchOptions(0, 1, 0, 4), nd.BatchOptions(1, 0, 256, 1), nd.BatchOptions(2, 1, 0, 2)]
-    best = autotune.tune_batch(probs, msg="fp16", cache=cache, candidates=cands, reps=2)
-    assert best.as_tuple() in [c.as_tuple() for c in cands]
-    again = autotune.tune_batch(probs, msg="fp16", cache=cache, candidates=[])
-    assert again.as_tuple() == best.as_tuple()
-    lanes = autotune.tune_code(mixed.codes[1], mixed.dllr[1], 20, msg="fp32", cache=cache, reps=2)
-    assert lanes in (1, 2) and mixed.codes[1].info["lanes_fp32"] == lanes
-    mixed.codes[1].tune("fp32", 0)
+    try:
+        best = autotune.tune_batch(probs, msg="fp16", cache=cache, candidates=cands, reps=2)
+        assert best.as_tuple() in [c.as_tuple() for c in cands]
+        tuned = [c.info["lanes_fp16"] for c in mixed.codes]
+        assert set(tuned) <= {1, 2, 4}
+        for c in mixed.codes:
+            c.tune("fp16", 0)
+        # the cached answer restores the per-code lanes too
+        again = autotune.tune_batch(probs, msg="fp16", cache=cache, candidates=[])
+        assert again.as_tuple() == best.as_tuple()
+        assert [c.info["lanes_fp16"] for c in mixed.codes] == tuned
+        lanes = autotune.tune_code(mixed.codes[1], mixed.dllr[1], 20, msg="fp32", cache=cache, reps=2)
+        assert lanes in (1, 2, 4) and mixed.codes[1].info["lanes_fp32"] == lanes
+    finally:
+        for c in mixed.codes:
+            c.tune("fp32", 0)
+            c.tune("fp16", 0)
 
 
 def test_async_batched_calls_in_flight(mixed):

@@ -240,13 +240,13 @@ def test_tune_arguments():
         print("degree 7, lanes", lanes, compare(g, r))
 
 
-@pytest.mark.parametrize("lanes", [1, 2])
+@pytest.mark.parametrize("lanes", [1, 2, 4])
 @pytest.mark.parametrize("msg", ["fp32", "fp16"])
 def test_lanes_per_check_node(lanes, msg):
-    """Both CN-phase mappings (one lane per CN visit, or two lanes sharing
-    it), chosen per message format, meet the parity bar on the n=2304
-    workload and on the QC code (FP32 messages: the two-tier bar; FP16:
-    the posterior error bound of the 16-bit formats)."""
+    """Every CN-phase mapping (one lane per CN visit, or two or four lanes
+    sharing it), chosen per message format, meets the parity bar on the
+    n=2304 workload and on the QC code (FP32 messages: the two-tier bar;
+    FP16: the posterior error bound of the 16-bit formats)."""
     for rec, snr in ((W.SWEEP, 2), (W.PRECISION, 0)):
         code = W.CODES[rec["code"]]()
         llr, _ = W.frames(rec, snr, num_frames=96, first_frame=500)
@@ -353,14 +353,14 @@ def test_degree_ten_variants(which, lanes):
     print(which, "lanes", lanes, compare(g, r))
 
 
-@pytest.mark.parametrize("lanes", [1, 2])
+@pytest.mark.parametrize("lanes", [1, 2, 4])
 @pytest.mark.parametrize("dv,dc,n", [(2, 4, 96), (3, 7, 336), (3, 8, 256), (3, 12, 384), (3, 16, 512),
                                      (4, 24, 480), (4, 32, 512)])
 def test_every_uniform_degree_variant(dv, dc, n, lanes):
     """Each padded-degree kernel variant on a regular code whose checks all
-    have that degree (the uniform form; degree 7 with two lanes runs the
-    degree-8 variant with one padding edge per check), both CN-lane
-    mappings."""
+    have that degree (the uniform form; degree 7 with two or four lanes runs
+    the degree-8 variant with one padding edge per check), with one, two and
+    four lanes per CN visit (four: the degree padded to a multiple of 4)."""
     code = regular_code(n, dv, dc, seed=3, girth6=False)
     rate = 1.0 - dv / dc
     llr, _ = make_frames(code.n, 64, 3.0 if dc <= 12 else 4.5, rate, seed=95)
