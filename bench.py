@@ -154,9 +154,10 @@ def bench_batched(args, torch, nd, W, dev, log):
     t0 = time.perf_counter()
     opts = autotune.tune_batch(probs, msg=rec["msg"], early_stop=rec["early_stop"],
                                cache=args.tune_cache)
-    lane_use = {}
+    lane_use = {}  # CN-lane mapping each problem runs with in the batch
     for p in probs:
-        lane_use[p.code.info["lanes_fp16"]] = lane_use.get(p.code.info["lanes_fp16"], 0) + 1
+        h = opts.lanes_per_cn or p.code.info["lanes_" + rec["msg"]]
+        lane_use[h] = lane_use.get(h, 0) + 1
     log(f"batched options {opts}, problems per CN-lane mapping {dict(sorted(lane_use.items()))} "
         f"({time.perf_counter() - t0:.1f} s)")
     batch = nd.Batch(probs, msg=rec["msg"], early_stop=rec["early_stop"], options=opts)
