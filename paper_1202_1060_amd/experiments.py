@@ -7,15 +7,20 @@ The paper compares, on MacKay's (504,252) (3,6) code with G = 12 and on its
 * GSBP (G disjoint CN groups), I_max = 1000;
 * NDGSBP (G groups by Step 1 with overlap ratio r = 0.4), with the iteration
   cap lowered to M I_max / (M + (G - 1) N_G r), so that every decoder may
-  spend the same number of CN updates.
+  spend the same number of CN updates;
+* NDGSBP with groups that make Step 1's free choices for a large CoCSG
+  (``grouping.cocsg_groups``, the open direction of Sec. V), same sizes and
+  budget.
 
 MacKay's matrices are not available; seeded (3,6) n=504 and (4,6) n=816
 codes with the same sizes stand in for them. Frames carry the all-zero
 codeword (the decoders are symmetric), generated on the GPU; every decode
 runs the library's kernels with FP32 messages and syndrome stop. BER counts
-codeword bits. NDGSBP runs twice: with one Step-1 grouping for the whole
-decode, and with a fresh Step-1 grouping for every iteration (as Step 4's
-return to Step 1 reads), drawn ahead of time up to the iteration cap.
+codeword bits. NDGSBP runs three times: with one Step-1 grouping for the
+whole decode, with a fresh Step-1 grouping for every iteration (as Step 4's
+return to Step 1 reads), drawn ahead of time up to the iteration cap, and
+with a fresh CoCSG-seeking grouping for every iteration. The mean CoCSG of
+each schedule is reported.
 
 Usage: python -m paper_1202_1060_amd.experiments [--frames F] [--out FILE]
 """
@@ -31,7 +36,7 @@ import torch
 
 from . import Code, decode
 from .grouping import (group_size, step1_groups, disjoint_random_groups,
-                       equal_complexity_iterations)
+                       equal_complexity_iterations, cocsg, cocsg_groups)
 
 SETUPS = {
     # code key, G, r, I_max of BP and GSBP, grouping seed
@@ -59,17 +64,27 @@ def decoders(code, setup):
     nd_groups = step1_groups(M, G, r, rng, N_G)
     gs_groups = disjoint_random_groups(M, G, rng)
     I_nd = equal_complexity_iterations(M, I, G, N_G, r)
-    sched = []
+    sched, sched_l = [], []
+    ell_step1, ell_cocsg = [], []
     for _ in range(I_nd):
-        sched += step1_groups(M, G, r, rng, N_G)
+        grp = step1_groups(M, G, r, rng, N_G)
+        sched += grp
+        ell_step1.append(cocsg(code, grp)[0])
+    for _ in range(I_nd):
+        grp = cocsg_groups(code, G, r, rng, N_G)
+        sched_l += grp
+        ell_cocsg.append(cocsg(code, grp)[0])
     per_iter = int(sum(len(g) for g in nd_groups))
     return [("bp", [np.arange(M, dtype=np.int32)], 0, I, M),
             ("gsbp", gs_groups, 0, I, M),
             ("ndgsbp", nd_groups, 0, I_nd, per_iter),
-            ("ndgsbp_regroup", sched, G, I_nd, per_iter)], dict(N_G=N_G, I_ndgsbp=I_nd)
+            ("ndgsbp_regroup", sched, G, I_nd, per_iter),
+            ("ndgsbp_cocsg_regroup", sched_l, G, I_nd, per_iter)], \
+        dict(N_G=N_G, I_ndgsbp=I_nd, ell_gsbp=cocsg(code, gs_groups)[0], ell_step1=float(np.mean(ell_step1)),
+             ell_cocsg=float(np.mean(ell_cocsg)))
 
 
-def run(code_key, ebn0s, frames, device, log=None, chunk=1 << 18):
+def run(code_key, ebn0s, frames, device, log=None, chunk=1 << 18, only=None):
     from ldpcgen import workloads as W
     from ldpcgen.channel import device_all_zero_llr
     from ldpcgen.gf2 import gf2_rank
@@ -82,6 +97,8 @@ def run(code_key, ebn0s, frames, device, log=None, chunk=1 << 18):
     for i, eb in enumerate(ebn0s):
         row = dict(ebn0=eb)
         for name, groups, gpi, cap, cn_per_iter in decs:
+            if only and name not in only:
+                continue
             dcode = Code(code, groups=groups, device=device.index or 0, groups_per_iteration=gpi)
             fe = be = it = 0
             t0 = time.perf_counter()
@@ -113,6 +130,7 @@ def run(code_key, ebn0s, frames, device, log=None, chunk=1 << 18):
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--codes", nargs="+", default=["n504", "n816"])
+    ap.add_argument("--decoders", nargs="+", default=None, help="subset of the decoders to run")
     ap.add_argument("--ebn0", nargs="+", type=float, default=[1.0, 1.5, 2.0, 2.5, 3.0])
     ap.add_argument("--frames", type=int, default=1 << 20)
     ap.add_argument("--out", default=None)
@@ -122,7 +140,7 @@ def main(argv=None):
     def log(*a):
         print(*a, file=sys.stderr, flush=True)
 
-    res = [run(c, args.ebn0, args.frames, dev, log) for c in args.codes]
+    res = [run(c, args.ebn0, args.frames, dev, log, only=args.decoders) for c in args.codes]
     text = json.dumps(res, indent=1)
     if args.out:
         with open(args.out, "w") as f:
