@@ -37,6 +37,7 @@ extern "C" {
 
 #define LDPC_GROUPS_WINDOWS 0
 #define LDPC_GROUPS_EXPLICIT 1
+#define LDPC_GROUPS_VN 2 /* VN groups: the vertical shuffled schedule (a baseline) */
 
 #define LDPC_FLAG_EARLY_STOP 0x1u /* stop a frame at its first zero syndrome (Step 4b) */
 #define LDPC_FLAG_MSG_FP16 0x2u   /* store CN->VN messages as IEEE binary16           */
@@ -69,14 +70,20 @@ typedef struct {
  *   iteration can use a fresh grouping (Step 4 returns to Step 1). 0: all
  *   groups every iteration. Decodes with R > 1 run in the LDS tier only.
  * Every CN must appear in some group (of every block) and at most once
- * within a group. */
+ * within a group.
+ * VN: the vertical group-shuffled schedule that Sec. I cites as prior art,
+ *   for comparison: group_ptr/group_cn list VN ids, each VN in exactly one
+ *   group; for group g, every CN->VN message into its VNs is computed from
+ *   the VN->CN messages as they stood before the group (eq. (1)), then
+ *   those VNs' posteriors are updated (eq. (2)-(3)). One grouping for every
+ *   iteration; LDS tier only; not in batches; FP32 or FP16 messages. */
 typedef struct {
     int32_t kind;
     int32_t num_groups;
     int32_t overlap;           /* WINDOWS only */
     int32_t wrap;              /* WINDOWS only */
-    const int32_t* group_ptr;  /* EXPLICIT only, host, num_groups + 1 */
-    const int32_t* group_cn;   /* EXPLICIT only, host                 */
+    const int32_t* group_ptr;  /* EXPLICIT and VN, host, num_groups + 1 */
+    const int32_t* group_cn;   /* EXPLICIT (CN ids) and VN (VN ids), host */
     int32_t groups_per_iteration; /* EXPLICIT only; 0 = num_groups   */
 } ldpc_grouping;
 

@@ -5,7 +5,8 @@ baseline leg of the benchmark may call it; the decoder library never does.
 It shares no code with the HIP path. Pieces:
 
 * ``ndgsbp_ref.c`` (built to ``libndgsbp_ref.so``): Steps 2-4 of Sec. II-C
-  with eq. (1)-(3) in FP64, threaded over frames.
+  with eq. (1)-(3) in FP64, threaded over frames; also the vertical
+  (VN-group) shuffled schedule that Sec. I cites as prior art.
 * ``windows``: the contiguous CN windows with overlap (Python, below).
 * ``literal``: a pure-Python version of the same schedule over a pluggable
   message algebra (real numbers or "which channel values reached here"
@@ -62,6 +63,8 @@ def _load():
                                             ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_double),
                                             ctypes.POINTER(ctypes.c_uint8), i32p,
                                             ctypes.POINTER(ctypes.c_uint8), ctypes.c_int]
+        lib.ref_decode_vertical.restype = ctypes.c_int
+        lib.ref_decode_vertical.argtypes = lib.ref_decode.argtypes
         lib.ref_phi_f64.restype = ctypes.c_double
         lib.ref_phi_f64.argtypes = [ctypes.c_double]
         lib.ref_boxplus.restype = ctypes.c_double
@@ -137,6 +140,46 @@ def decode(code, groups, llr, max_iter: int, early_stop: bool, nthreads: int = 0
     if rc < 0:
         raise ValueError(f"ref_decode rejected its input ({rc})")
     return dict(post=post, hard=hard, iters=iters, syn_ok=syn, threads=rc)
+
+
+def decode_vertical(code, vn_groups, llr, max_iter: int, early_stop: bool, nthreads: int = 0):
+    """Vertical group-shuffled decoding (the prior-art schedule Sec. I
+    contrasts with: VN groups processed in order; for each, the CN->VN
+    messages into its VNs from the VN->CN messages as they stood before the
+    group, eq. (1), then those VNs' VN->CN messages, eq. (2)). Same inputs
+    and outputs as ``decode`` with VN-id groups."""
+    lib = _load()
+    llr = np.ascontiguousarray(llr, dtype=np.float32)
+    if llr.ndim == 1:
+        llr = llr[None, :]
+    F, n = llr.shape
+    assert n == code.n
+    row_ptr = np.ascontiguousarray(code.row_ptr, dtype=np.int32)
+    col = np.ascontiguousarray(code.col_idx, dtype=np.int32)
+    gptr, gvn = _groups_csr(vn_groups)
+    post = np.zeros((F, n), dtype=np.float64)
+    hard = np.zeros((F, n), dtype=np.uint8)
+    iters = np.zeros(F, dtype=np.int32)
+    syn = np.zeros(F, dtype=np.uint8)
+    i32 = ctypes.c_int32
+    rc = lib.ref_decode_vertical(code.m, n, _p(row_ptr, i32), _p(col, i32), len(vn_groups), _p(gptr, i32),
+                                 _p(gvn, i32), _p(llr, ctypes.c_float), F, int(max_iter), int(bool(early_stop)),
+                                 _p(post, ctypes.c_double), _p(hard, ctypes.c_uint8), _p(iters, i32),
+                                 _p(syn, ctypes.c_uint8), int(nthreads))
+    if rc < 0:
+        raise ValueError(f"ref_decode_vertical rejected its input ({rc})")
+    return dict(post=post, hard=hard, iters=iters, syn_ok=syn, threads=rc)
+
+
+def decode_vertical_with_sensitivity(code, vn_groups, llr, max_iter: int, early_stop: bool, nthreads: int = 0):
+    """decode_vertical plus the one-ulp sensitivity of decode_with_sensitivity."""
+    ref = decode_vertical(code, vn_groups, llr, max_iter, early_stop, nthreads)
+    ctl = decode_vertical(code, vn_groups, perturb_one_ulp(llr), max_iter, early_stop, nthreads)
+    sens = np.abs(ctl["post"] - ref["post"]).max(axis=1)
+    flip = np.any(ctl["hard"] != ref["hard"], axis=1) | (ctl["iters"] != ref["iters"])
+    sens[flip] = np.inf
+    ref["sens"] = sens
+    return ref
 
 
 def perturb_one_ulp(llr, seed: int = 12345):

@@ -71,6 +71,7 @@ typedef struct {
     const int32_t* gcn;     /* gptr[G] */
     int32_t* vptr;          /* N+1: edges of VN n are vedge[vptr[n]..vptr[n+1]) */
     int32_t* vedge;         /* E   */
+    int32_t* ecn;           /* E: the CN of each edge */
     const float* llr;
     int F, max_iter, early_stop;
     double* post;
@@ -79,6 +80,7 @@ typedef struct {
     uint8_t* syn_ok;
     int nthreads;
     int gper; /* groups per iteration: iteration l uses block (l-1) mod (G / gper) */
+    int vertical; /* groups hold VN ids: the vertical group-shuffled schedule */
 } ref_job;
 
 typedef struct {
@@ -102,6 +104,35 @@ static void decode_frame(const ref_job* J, int f, double* Lch, double* Lcv, doub
     for (int l = 1; l <= J->max_iter; ++l) {
         const int g0 = ((l - 1) % R) * J->gper;
         for (int g = g0; g < g0 + J->gper; ++g, ++visit) {
+            if (J->vertical) {
+                /* Vertical group-shuffled BP (the prior-art schedule of Sec. I,
+                   VN groups): (a) for every n of the group and m in M(n), the
+                   CN->VN message of eq. (1) from the VN->CN messages as they
+                   stood before the group; (b) eq. (2) for every n of the
+                   group and every m in M(n). */
+                for (int q = J->gptr[g]; q < J->gptr[g + 1]; ++q) {
+                    const int n = J->gcn[q];
+                    for (int a = J->vptr[n]; a < J->vptr[n + 1]; ++a) {
+                        const int e = J->vedge[a];
+                        const int m = J->ecn[e];
+                        const int b = J->row_ptr[m], d = J->row_ptr[m + 1] - b;
+                        int k = 0;
+                        for (int j = 0; j < d; ++j)
+                            if (b + j != e) tmp[k++] = Lvc[b + j];
+                        Lcv[e] = ref_boxplus(tmp, k);
+                    }
+                }
+                for (int q = J->gptr[g]; q < J->gptr[g + 1]; ++q) {
+                    const int n = J->gcn[q];
+                    for (int a = J->vptr[n]; a < J->vptr[n + 1]; ++a) {
+                        double s = Lch[n];
+                        for (int c = J->vptr[n]; c < J->vptr[n + 1]; ++c)
+                            if (c != a) s += Lcv[J->vedge[c]];
+                        Lvc[J->vedge[a]] = s;
+                    }
+                }
+                continue;
+            }
             /* (a) CN update, eq. (1): Lvc is not written in this phase, so every
                CN of the group reads the pre-group VN->CN messages. */
             for (int q = J->gptr[g]; q < J->gptr[g + 1]; ++q) {
@@ -190,9 +221,9 @@ static void* worker(void* arg) {
  * iters F ints, syn_ok F bytes. nthreads <= 0 uses every online CPU.
  * Returns the number of threads used, or a negative value on bad input.
  */
-int ref_decode_schedule(int M, int N, const int32_t* row_ptr, const int32_t* col, int G, const int32_t* gptr,
-                        const int32_t* gcn, int gper, const float* llr, int F, int max_iter, int early_stop,
-                        double* post, uint8_t* hard, int32_t* iters, uint8_t* syn_ok, int nthreads) {
+static int run_job(int M, int N, const int32_t* row_ptr, const int32_t* col, int G, const int32_t* gptr,
+                   const int32_t* gcn, int gper, int vertical, const float* llr, int F, int max_iter,
+                   int early_stop, double* post, uint8_t* hard, int32_t* iters, uint8_t* syn_ok, int nthreads) {
     if (M <= 0 || N <= 0 || G <= 0 || F < 0 || max_iter < 1) return -1;
     if (gper == 0) gper = G;
     if (gper < 0 || G % gper) return -1;
@@ -202,22 +233,25 @@ int ref_decode_schedule(int M, int N, const int32_t* row_ptr, const int32_t* col
     for (int e = 0; e < E; ++e)
         if (col[e] < 0 || col[e] >= N) return -1;
     for (int q = 0; q < gptr[G]; ++q)
-        if (gcn[q] < 0 || gcn[q] >= M) return -1;
+        if (gcn[q] < 0 || gcn[q] >= (vertical ? N : M)) return -1;
     if (F == 0) return 0;
     ref_job J;
     memset(&J, 0, sizeof J);
-    J.M = M; J.N = N; J.E = E; J.G = G; J.gper = gper;
+    J.M = M; J.N = N; J.E = E; J.G = G; J.gper = gper; J.vertical = vertical;
     J.row_ptr = row_ptr; J.col = col; J.gptr = gptr; J.gcn = gcn;
     J.llr = llr; J.F = F; J.max_iter = max_iter; J.early_stop = early_stop;
     J.post = post; J.hard = hard; J.iters = iters; J.syn_ok = syn_ok;
     /* VN -> edge adjacency (M(n)), edges listed in increasing edge id */
     J.vptr = calloc((size_t)N + 1, sizeof(int32_t));
     J.vedge = malloc(sizeof(int32_t) * (E + 1));
+    J.ecn = malloc(sizeof(int32_t) * (E + 1));
     int32_t* fill = calloc((size_t)N, sizeof(int32_t));
-    if (!J.vptr || !J.vedge || !fill) {
-        free(J.vptr); free(J.vedge); free(fill);
+    if (!J.vptr || !J.vedge || !J.ecn || !fill) {
+        free(J.vptr); free(J.vedge); free(J.ecn); free(fill);
         return -2;
     }
+    for (int m = 0; m < M; ++m)
+        for (int e = row_ptr[m]; e < row_ptr[m + 1]; ++e) J.ecn[e] = m;
     for (int e = 0; e < E; ++e) J.vptr[col[e] + 1]++;
     for (int n = 0; n < N; ++n) J.vptr[n + 1] += J.vptr[n];
     for (int e = 0; e < E; ++e) {
@@ -241,7 +275,24 @@ int ref_decode_schedule(int M, int N, const int32_t* row_ptr, const int32_t* col
     free(tk);
     free(J.vptr);
     free(J.vedge);
+    free(J.ecn);
     return T;
+}
+
+int ref_decode_schedule(int M, int N, const int32_t* row_ptr, const int32_t* col, int G, const int32_t* gptr,
+                        const int32_t* gcn, int gper, const float* llr, int F, int max_iter, int early_stop,
+                        double* post, uint8_t* hard, int32_t* iters, uint8_t* syn_ok, int nthreads) {
+    return run_job(M, N, row_ptr, col, G, gptr, gcn, gper, 0, llr, F, max_iter, early_stop, post, hard, iters,
+                   syn_ok, nthreads);
+}
+
+/* Vertical group-shuffled decoding: groups gptr[G+1], gvn over VN ids (each
+ * processed as in decode_frame), the same groups every iteration. */
+int ref_decode_vertical(int M, int N, const int32_t* row_ptr, const int32_t* col, int G, const int32_t* gptr,
+                        const int32_t* gvn, const float* llr, int F, int max_iter, int early_stop, double* post,
+                        uint8_t* hard, int32_t* iters, uint8_t* syn_ok, int nthreads) {
+    return run_job(M, N, row_ptr, col, G, gptr, gvn, 0, 1, llr, F, max_iter, early_stop, post, hard, iters,
+                   syn_ok, nthreads);
 }
 
 /* The same with one grouping for every iteration. */

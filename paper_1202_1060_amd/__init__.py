@@ -41,27 +41,29 @@ def ldpc_last_error() -> str:
     return _native.load().ldpc_last_error().decode(errors="replace")
 
 
-def ldpc_code_create(m, n, row_ptr, col_idx, *, windows=None, groups=None, device=0,
+def ldpc_code_create(m, n, row_ptr, col_idx, *, windows=None, groups=None, vn_groups=None, device=0,
                      groups_per_iteration=0):
     """Create a device code handle (see include/ndgsbp.h).
 
     ``windows=(G, overlap, wrap)`` or ``groups=[CN-id arrays]`` (in order;
     with ``groups_per_iteration`` = Gp, iteration l uses the l-th block of
-    Gp groups, cyclically). Returns the opaque handle (int)."""
+    Gp groups, cyclically), or ``vn_groups=[VN-id arrays]`` for the vertical
+    group-shuffled schedule. Returns the opaque handle (int)."""
     rp, ci = _i32(row_ptr), _i32(col_idx)
     h = _native.ldpc_h_csr(int(m), int(n), int(len(ci)), _ptr(rp), _ptr(ci))
-    if (windows is None) == (groups is None):
-        raise ValueError("give exactly one of windows= or groups=")
+    if sum(x is not None for x in (windows, groups, vn_groups)) != 1:
+        raise ValueError("give exactly one of windows=, groups= or vn_groups=")
     keep = []
     if windows is not None:
         G, o, wrap = windows
         g = _native.ldpc_grouping(LDPC_GROUPS_WINDOWS, int(G), int(o), int(bool(wrap)), None, None, 0)
     else:
-        gptr = _i32(np.concatenate([[0], np.cumsum([len(x) for x in groups])]))
-        gcn = _i32(np.concatenate([np.asarray(x) for x in groups]) if len(groups) else [])
+        lists = groups if groups is not None else vn_groups
+        gptr = _i32(np.concatenate([[0], np.cumsum([len(x) for x in lists])]))
+        gcn = _i32(np.concatenate([np.asarray(x) for x in lists]) if len(lists) else [])
         keep += [gptr, gcn]
-        g = _native.ldpc_grouping(LDPC_GROUPS_EXPLICIT, len(groups), 0, 0, _ptr(gptr), _ptr(gcn),
-                                  int(groups_per_iteration))
+        kind = LDPC_GROUPS_EXPLICIT if groups is not None else _native.LDPC_GROUPS_VN
+        g = _native.ldpc_grouping(kind, len(lists), 0, 0, _ptr(gptr), _ptr(gcn), int(groups_per_iteration))
     out = ctypes.c_void_p()
     _native.check(_native.load().ldpc_code_create(ctypes.byref(h), ctypes.byref(g), int(device), ctypes.byref(out)))
     return out.value
@@ -99,10 +101,10 @@ class Code:
     """Owns a device code handle. ``code`` is any object with m, n, row_ptr,
     col_idx (e.g. ldpcgen.Code)."""
 
-    def __init__(self, code, *, windows=None, groups=None, device=0, groups_per_iteration=0):
+    def __init__(self, code, *, windows=None, groups=None, vn_groups=None, device=0, groups_per_iteration=0):
         self.m, self.n = int(code.m), int(code.n)
         self.handle = ldpc_code_create(code.m, code.n, code.row_ptr, code.col_idx,
-                                       windows=windows, groups=groups, device=device,
+                                       windows=windows, groups=groups, vn_groups=vn_groups, device=device,
                                        groups_per_iteration=groups_per_iteration)
         self.info = ldpc_code_query(self.handle)
         self.device = device

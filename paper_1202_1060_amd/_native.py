@@ -18,6 +18,7 @@ LDPC_EUNSUPPORTED = -4
 
 LDPC_GROUPS_WINDOWS = 0
 LDPC_GROUPS_EXPLICIT = 1
+LDPC_GROUPS_VN = 2
 
 LDPC_FLAG_EARLY_STOP = 0x1
 LDPC_FLAG_MSG_FP16 = 0x2

@@ -39,6 +39,7 @@ struct ldpc_code {
     int64_t nnz;
     int32_t G;  // groups per iteration
     int32_t R;  // iteration blocks: iteration l uses groups ((l-1) mod R) * G ..
+    bool vertical = false;  // VN groups (the vertical schedule)
     int64_t cn_visits;
     int64_t edge_updates;
     int32_t max_cn_degree;

@@ -147,6 +147,53 @@ int expand_groups(const ldpc_grouping* g, int m, std::vector<std::vector<int32_t
     return LDPC_OK;
 }
 
+// VN groups (the vertical schedule): `vgroup` = the group of every VN; the
+// visits of group g are the CNs adjacent to its VNs, in increasing order.
+int expand_vn_groups(const ldpc_h_csr* H, const ldpc_grouping* g, std::vector<int32_t>& vgroup,
+                     std::vector<std::vector<int32_t>>& out) {
+    const int m = H->m, n = H->n;
+    if (g->num_groups < 1) return fail(LDPC_EINVAL, "num_groups must be >= 1");
+    if (!g->group_ptr || !g->group_cn) return fail(LDPC_EINVAL, "VN grouping needs group_ptr/group_cn");
+    if (g->group_ptr[0] != 0) return fail(LDPC_EINVAL, "group_ptr[0] must be 0");
+    if (g->groups_per_iteration != 0) return fail(LDPC_EINVAL, "groups_per_iteration needs CN groups");
+    vgroup.assign(n, -1);
+    for (int k = 0; k < g->num_groups; ++k) {
+        if (g->group_ptr[k + 1] < g->group_ptr[k]) return fail(LDPC_EINVAL, "group_ptr not monotone");
+        if (g->group_ptr[k + 1] == g->group_ptr[k]) return fail(LDPC_EINVAL, "empty group");
+        for (int32_t q = g->group_ptr[k]; q < g->group_ptr[k + 1]; ++q) {
+            const int32_t v = g->group_cn[q];
+            if (v < 0 || v >= n) return fail(LDPC_EINVAL, "group VN out of range");
+            if (vgroup[v] >= 0) return fail(LDPC_EINVAL, "VN " + std::to_string(v) + " in two groups");
+            vgroup[v] = k;
+        }
+    }
+    for (int v = 0; v < n; ++v)
+        if (vgroup[v] < 0) return fail(LDPC_EINVAL, "VN " + std::to_string(v) + " belongs to no group");
+    out.assign(g->num_groups, {});
+    std::vector<int32_t> last(m, -1);
+    for (int c = 0; c < m; ++c)
+        for (int32_t q = H->row_ptr[c]; q < H->row_ptr[c + 1]; ++q) {
+            const int32_t k = vgroup[H->col_idx[q]];
+            if (last[c] == k) continue;  // rows are scanned in CN order, so
+            last[c] = k;                 // each group's list stays sorted
+            if (out[k].empty() || out[k].back() != c) out[k].push_back(c);
+        }
+    // a group whose VNs have no edge has nothing to visit: drop it and
+    // renumber the others
+    std::vector<int32_t> renum(out.size(), -1);
+    size_t kept = 0;
+    for (size_t k = 0; k < out.size(); ++k)
+        if (!out[k].empty()) {
+            renum[k] = (int32_t)kept;
+            if (kept != k) out[kept].swap(out[k]);
+            ++kept;
+        }
+    out.resize(kept);
+    if (out.empty()) return fail(LDPC_EINVAL, "no group has an edge");
+    for (int v = 0; v < n; ++v) vgroup[v] = renum[vgroup[v]];
+    return LDPC_OK;
+}
+
 // LDS of a workgroup (layout in ndgsbp_internal.h).
 size_t float_bytes(const ldpc_code* c) { return align16((size_t)(c->ds_start + c->max_slots) * 4); }
 size_t msg_bytes(const ldpc_code* c, const Layout& l, MsgKind kind) {
@@ -312,7 +359,8 @@ int check_lds(const ldpc_code* c, const Layout& lay, MsgKind kind) {
 // per frame.
 int set_blocks(MsgKind kind, int D, bool uniform, bool table, int num_cus, int64_t frames, LaunchShape& shape) {
     int per_cu = 0;
-    hipError_t oe = decode_occupancy(kind, D, uniform, shape.lanes, table, shape.threads, shape.lds_bytes, &per_cu);
+    const int mode = table ? 1 : shape.vertical ? 2 : 0;
+    hipError_t oe = decode_occupancy(kind, D, uniform, shape.lanes, mode, shape.threads, shape.lds_bytes, &per_cu);
     if (oe != hipSuccess) return hip_fail(oe, "occupancy query");
     if (per_cu < 1) return fail(LDPC_EUNSUPPORTED, "kernel variant cannot be resident");
     shape.blocks = (int)std::min<int64_t>((int64_t)per_cu * num_cus, frames);
@@ -468,6 +516,7 @@ int form_classes(const ldpc_problem* probs, int32_t count, MsgKind kind, const l
         }
         if (q.num_frames == 0) continue;
         if (!q.llr || !q.hard || !q.iters) return fail(LDPC_EINVAL, at + "llr, hard and iters are required");
+        if (q.code->vertical) return fail(LDPC_EUNSUPPORTED, at + "codes with VN groups are not batched");
         const int h = o.lanes_per_cn ? o.lanes_per_cn : q.code->lanes_for[kind];
         const Layout& lay = q.code->lay[h - 1];
         if (!lay.valid) return fail(LDPC_EUNSUPPORTED, at + "no kernel variant with that mapping");
@@ -736,7 +785,12 @@ int ldpc_code_create(const ldpc_h_csr* H, const ldpc_grouping* grouping, int32_t
     }
     if (maxd > kMaxDegree) return fail(LDPC_EUNSUPPORTED, "CN degree above 32");
     std::vector<std::vector<int32_t>> groups;
-    int rc = expand_groups(grouping, m, groups);
+    // vertical schedule: the group of every VN; each VN group becomes the
+    // visits of the CNs adjacent to it, whose edges into other groups are
+    // inputs only
+    const bool vertical = grouping && grouping->kind == LDPC_GROUPS_VN;
+    std::vector<int32_t> vgroup;
+    int rc = vertical ? expand_vn_groups(H, grouping, vgroup, groups) : expand_groups(grouping, m, groups);
     if (rc) return rc;
 
     ldpc_code* c = new (std::nothrow) ldpc_code();
@@ -748,6 +802,7 @@ int ldpc_code_create(const ldpc_h_csr* H, const ldpc_grouping* grouping, int32_t
     c->R = (grouping->groups_per_iteration > 0) ? (int32_t)groups.size() / grouping->groups_per_iteration : 1;
     c->G = (int32_t)groups.size() / c->R;
     c->max_cn_degree = maxd;
+    c->vertical = vertical;
     c->max_vn_degree = n ? *std::max_element(vdeg.begin(), vdeg.end()) : 0;
 
     // float index of the first delta slot: right after the posteriors
@@ -768,12 +823,16 @@ int ldpc_code_create(const ldpc_h_csr* H, const ldpc_grouping* grouping, int32_t
     c->edge_updates = 0;
     c->max_group_visits = 0;
     c->max_slots = 0;
-    for (const auto& grp : groups) {
+    for (size_t gidx = 0; gidx < groups.size(); ++gidx) {
+        const auto& grp = groups[gidx];
+        // an edge is an input only when its VN is outside a vertical group
+        auto input_only = [&](int32_t v) { return vertical && vgroup[v] != (int32_t)gidx; };
         // multiplicity of each VN inside the group
         seen_order.clear();
         for (int32_t cn : grp)
             for (int32_t q = H->row_ptr[cn]; q < H->row_ptr[cn + 1]; ++q) {
                 const int32_t v = H->col_idx[q];
+                if (input_only(v)) continue;
                 if (cnt[v]++ == 0) seen_order.push_back(v);
             }
         // consecutive delta slots for every VN with two or more edges here,
@@ -789,15 +848,17 @@ int ldpc_code_create(const ldpc_h_csr* H, const ldpc_grouping* grouping, int32_t
             delete c;
             return fail(LDPC_EUNSUPPORTED, "too many delta slots in one group");
         }
-        int64_t edges = 0;
+        int64_t edges = 0, outputs = 0;
         for (int32_t cn : grp) {
             const int32_t b = H->row_ptr[cn], d = H->row_ptr[cn + 1] - b;
             vcn.push_back(cn);
             for (int32_t k = 0; k < d; ++k) {
                 const int32_t v = H->col_idx[b + k];
-                const int32_t tgt = cnt[v] >= 2 ? ds_start + first_slot[v] + next_fill[v]++ : v;
+                // input-only edges add back into the scratch word n
+                const int32_t tgt = input_only(v) ? n : cnt[v] >= 2 ? ds_start + first_slot[v] + next_fill[v]++ : v;
                 esrc.push_back((uint32_t)v);
                 edst.push_back((uint32_t)tgt);
+                outputs += input_only(v) ? 0 : 1;
             }
             vdeg_of.push_back(vdeg_of.back() + d);
             edges += d;
@@ -807,7 +868,7 @@ int ldpc_code_create(const ldpc_h_csr* H, const ldpc_grouping* grouping, int32_t
             first_slot[v] = -1;
             next_fill[v] = 0;
         }
-        c->edge_updates += edges;
+        c->edge_updates += outputs;
         max_edges = std::max(max_edges, edges);
         c->cn_visits += (int64_t)grp.size();
         c->max_group_visits = std::max<int32_t>(c->max_group_visits, (int32_t)grp.size());
@@ -997,9 +1058,16 @@ int ldpc_decode(ldpc_code_t c, const float* llr, int32_t num_frames, int32_t max
 
     DeviceGuard guard(c->device);
     if (!guard.ok) return fail(LDPC_EHIP, "cannot select the code's device");
-    if ((flags & LDPC_FLAG_TIER_HBM) || lds_bytes(c, lay, kind) > c->max_lds)
+    if (c->vertical) {
+        if ((flags & LDPC_FLAG_TIER_HBM) || lds_bytes(c, lay, kind) > c->max_lds)
+            return fail(LDPC_EUNSUPPORTED, "the vertical schedule runs in the LDS tier only");
+        if (kind == kMsgBF16 || lay.H > 2)
+            return fail(LDPC_EUNSUPPORTED, "the vertical schedule takes FP32 or FP16 messages, one or two lanes");
+    } else if ((flags & LDPC_FLAG_TIER_HBM) || lds_bytes(c, lay, kind) > c->max_lds) {
         return decode_hbm(c, llr, num_frames, max_iter, flags, hard, post, iters, syn_ok, (hipStream_t)hip_stream);
+    }
     LaunchShape shape;
+    shape.vertical = c->vertical;
     shape.lanes = lay.H;
     shape.threads = threads_for(c, lay);
     shape.lds_bytes = lds_bytes(c, lay, kind);

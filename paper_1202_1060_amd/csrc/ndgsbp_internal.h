@@ -92,10 +92,11 @@ struct DecodeArgs {
 };
 
 struct LaunchShape {
-    int lanes;       // lanes per CN visit (1 or 2)
+    int lanes;       // lanes per CN visit (1, 2 or 4)
     int threads;     // workgroup size
     int blocks;      // persistent workgroups
     size_t lds_bytes;
+    bool vertical = false;  // VN groups (the vertical schedule)
 };
 
 enum MsgKind { kMsgF32 = 0, kMsgF16 = 1, kMsgBF16 = 2 };
@@ -105,7 +106,8 @@ hipError_t launch_decode(const DecodeArgs& a, MsgKind kind, int dmax, bool unifo
                          hipStream_t stream);
 // Resident workgroups per CU of a kernel variant.
 // `table`: the batched kernel (problems read from a device table).
-hipError_t decode_occupancy(MsgKind kind, int dmax, bool uniform, int lanes, bool table, int threads,
+// mode: 0 one problem, 1 a batch's problem table, 2 the vertical schedule
+hipError_t decode_occupancy(MsgKind kind, int dmax, bool uniform, int lanes, int mode, int threads,
                             size_t lds_bytes, int* blocks_per_cu);
 int max_threads_for_degree(int dmax);
 // Bytes of the message rows of one CN.

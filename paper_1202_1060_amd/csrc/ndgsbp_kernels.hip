@@ -24,6 +24,8 @@
 // before the group, as eq. (1) prescribes for a group processed in parallel.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "ndgsbp_cn.h"
 #include "ndgsbp_internal.h"
 #include "ndgsbp_math.h"
@@ -129,8 +131,10 @@ __device__ __forceinline__ void load_visit(const Problem& p, int j0, int item, i
 }
 
 // One lane's share of a CN visit: eq. (1) for its edges (cn_core), then
-// the add-back into LDS.
-template <class M, int D, bool UNI, int H>
+// the add-back into LDS. VERT (the vertical, VN-group schedule): an edge
+// whose add-back target is the scratch word (ta = 4n) is an input only, its
+// VN being outside the group: its message keeps its old bits.
+template <class M, int D, bool UNI, int H, bool VERT>
 __device__ __forceinline__ void cn_visit(const DecodeArgs& a, const Problem& p, const VisitRegs<D / H>& r,
                                          uint32_t h) {
     constexpr int DH = D / H;
@@ -146,6 +150,11 @@ __device__ __forceinline__ void cn_visit(const DecodeArgs& a, const Problem& p, 
         real[k] = r.pa[k] != p.pad_b;
     }
     cn_core<M, DH, UNI, H>(pv, lo, real, a.ymin, a.ymax, a.cmin, st, wv);
+    if constexpr (VERT) {
+#pragma unroll
+        for (int k = 0; k < DH; ++k)
+            if (r.ta[k] == p.pad_b) st[k] = M::pack(lo[k]);  // exact: lo came from these bits
+    }
 #pragma unroll
     for (int k = 0; k < DH; ++k) lds_f32(r.ta[k]) = wv[k];
     R::store(row, st);
@@ -300,8 +309,13 @@ __device__ __forceinline__ void write_outputs(const DecodeArgs& a, const Problem
 
 // TABLE: the launch reads its problems from a.table (batched decoding);
 // otherwise it decodes a.p0, whose fields stay kernel arguments.
-template <class M, int D, bool UNI, int H, bool TABLE>
+// MODE 0: one problem in the kernel arguments; 1 (TABLE): the problems of a
+// batch from a device table; 2 (VERT): one problem whose groups are VN
+// groups (the vertical schedule).
+template <class M, int D, bool UNI, int H, int MODE>
 __global__ __launch_bounds__(MaxThreads<D>::value) void ndgsbp_kernel(DecodeArgs a) {
+    constexpr bool TABLE = MODE == 1;
+    constexpr bool VERT = MODE == 2;
     constexpr int DH = D / H;
     constexpr int SD = (D + 3) / 4 * 4;  // syndrome row stride (entries)
     constexpr int SYNK = SynChecks<SD, H>::value;
@@ -354,12 +368,12 @@ __global__ __launch_bounds__(MaxThreads<D>::value) void ndgsbp_kernel(DecodeArgs
             // this lane's first fix-up entry of the group, fetched before the CN phase
             const int q0 = table_i32(p.fix_ptr, g), q1 = table_i32(p.fix_ptr, g + 1);
             const uint2 fix0 = q0 + tid < q1 ? p.fix[q0 + tid] : make_uint2(0u, 0u);
-            if (have_cur) cn_visit<M, D, UNI, H>(a, p, cur, lh);
+            if (have_cur) cn_visit<M, D, UNI, H, VERT>(a, p, cur, lh);
             const int j0 = table_i32(p.visit_ptr, g), j1 = table_i32(p.visit_ptr, g + 1);
             for (int item = vitem + nvitem; item < j1 - j0; item += nvitem) {
                 VisitRegs<DH> extra;
                 load_visit<DH, H>(p, j0, item, lh, extra);
-                cn_visit<M, D, UNI, H>(a, p, extra, lh);
+                cn_visit<M, D, UNI, H, VERT>(a, p, extra, lh);
             }
             __syncthreads();
             if (q1 > q0) {
@@ -447,11 +461,26 @@ __global__ __launch_bounds__(MaxThreads<D>::value) void ndgsbp_kernel(DecodeArgs
     }
 }
 
+// The vertical schedule is built for 32- and 16-bit messages with one or
+// two lanes per CN visit.
+template <class M, int H>
+constexpr bool kVertical = H <= 2 && !std::is_same<M, MsgBF16>::value;
+
+template <class M, int D, bool UNI, int H>
+const void* kernel_for(int mode) {
+    if (mode == 1) return reinterpret_cast<const void*>(&ndgsbp_kernel<M, D, UNI, H, 1>);
+    if (mode == 2) {
+        if constexpr (kVertical<M, H>) return reinterpret_cast<const void*>(&ndgsbp_kernel<M, D, UNI, H, 2>);
+        return nullptr;
+    }
+    return reinterpret_cast<const void*>(&ndgsbp_kernel<M, D, UNI, H, 0>);
+}
+
 template <class M, int D, bool UNI, int H>
 struct LaunchF {
     static hipError_t run(const DecodeArgs* a, const LaunchShape* sh, hipStream_t s) {
-        const void* fn = a->table ? reinterpret_cast<const void*>(&ndgsbp_kernel<M, D, UNI, H, true>)
-                                  : reinterpret_cast<const void*>(&ndgsbp_kernel<M, D, UNI, H, false>);
+        const void* fn = kernel_for<M, D, UNI, H>(a->table ? 1 : sh->vertical ? 2 : 0);
+        if (!fn) return hipErrorInvalidValue;
         hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh->lds_bytes);
         if (e != hipSuccess) return e;
         DecodeArgs copy = *a;
@@ -462,9 +491,9 @@ struct LaunchF {
 
 template <class M, int D, bool UNI, int H>
 struct OccupancyF {
-    static hipError_t run(bool table, int threads, size_t lds, int* out) {
-        const void* fn = table ? reinterpret_cast<const void*>(&ndgsbp_kernel<M, D, UNI, H, true>)
-                               : reinterpret_cast<const void*>(&ndgsbp_kernel<M, D, UNI, H, false>);
+    static hipError_t run(int mode, int threads, size_t lds, int* out) {
+        const void* fn = kernel_for<M, D, UNI, H>(mode);
+        if (!fn) return hipErrorInvalidValue;
         hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
         return hipOccupancyMaxActiveBlocksPerMultiprocessor(out, fn, threads, lds);
@@ -531,9 +560,9 @@ hipError_t launch_decode(const DecodeArgs& a, MsgKind kind, int dmax, bool unifo
     return dispatch<LaunchF>(kind, dmax, uniform, shape.lanes, &a, &shape, stream);
 }
 
-hipError_t decode_occupancy(MsgKind kind, int dmax, bool uniform, int lanes, bool table, int threads,
+hipError_t decode_occupancy(MsgKind kind, int dmax, bool uniform, int lanes, int mode, int threads,
                             size_t lds_bytes, int* blocks_per_cu) {
-    return dispatch<OccupancyF>(kind, dmax, uniform, lanes, table, threads, lds_bytes, blocks_per_cu);
+    return dispatch<OccupancyF>(kind, dmax, uniform, lanes, mode, threads, lds_bytes, blocks_per_cu);
 }
 
 }  // namespace ndgsbp

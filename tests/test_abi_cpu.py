@@ -159,3 +159,22 @@ def test_regrouping_argument_checks(nd):
         nd.ldpc_code_create(m, n, rp, ci, groups=[[0, 1], [2, 3], [0, 1], [2]], groups_per_iteration=2)
     assert ei.value.code == nd.LDPC_EINVAL
     assert "block 1" in nd.ldpc_last_error()
+
+
+@pytest.mark.parametrize("vn_groups,what", [
+    ([[0, 1], [1, 2, 3]], "two groups"),
+    ([[0, 1], [2]], "no group"),
+    ([[0, 1], [2, 4]], "out of range"),
+    ([[0, 1], []], "empty group"),
+])
+def test_vertical_grouping_argument_checks(nd, vn_groups, what):
+    """VN groups (the vertical schedule) must partition the VNs; they are
+    checked before any device work."""
+    rp, col = [0, 2, 4, 6], [0, 1, 1, 2, 2, 3]
+    with pytest.raises(nd.LdpcError) as ei:
+        nd.ldpc_code_create(3, 4, rp, col, vn_groups=vn_groups)
+    assert ei.value.code == nd.LDPC_EINVAL
+    assert what in nd.ldpc_last_error()
+    with pytest.raises(nd.LdpcError) as ei:
+        nd.ldpc_code_create(3, 4, rp, col, vn_groups=[[0, 1], [2, 3]], groups_per_iteration=1)
+    assert ei.value.code == nd.LDPC_EINVAL

@@ -346,3 +346,47 @@ def test_early_stop_iteration_count_is_first_zero_syndrome():
             if it > 1:
                 fp = oracle.decode(code, groups, llr[f:f + 1], it - 1, False, 1)
                 assert fp["syn_ok"][0] == 0
+
+
+# --- vertical (VN-group) shuffled schedule, the prior art of Sec. I --------
+
+@pytest.mark.parametrize("seed", range(3))
+def test_vertical_one_group_is_flooding(seed):
+    """One VN group holding every VN is flooding BP, bit for bit."""
+    code = regular_code(96, 3, 6, seed=10 + seed, girth6=True)
+    llr, _ = make_frames(code.n, 24, 1.5, 0.5, seed=70 + seed)
+    a = oracle.decode_vertical(code, [np.arange(code.n)], llr, 8, False, nthreads=1)
+    b = oracle.decode(code, [np.arange(code.m)], llr, 8, False, nthreads=1)
+    assert np.array_equal(a["post"], b["post"])
+
+
+def test_vertical_schedule_closed_form():
+    """c1 = {v0, v1}, c2 = {v1, v2} with VN groups {v1} then {v0, v2}: in the
+    first sub-iteration v1 takes L0 (through c1) and L2 (through c2) and
+    sends L1 + L2 to c1 and L1 + L0 to c2; in the second, v0 and v2 take
+    those, so after one iteration every posterior is L0 + L1 + L2 (flooding
+    gives L0 + L1 at v0). A degree-2 check passes its other input through
+    unchanged (phi is an involution)."""
+    code = Code.from_rows([[0, 1], [1, 2]], 3)
+    L = np.array([[0.7, -1.3, 2.1]], dtype=np.float32)
+    Ld = L.astype(np.float64)[0]
+    v = oracle.decode_vertical(code, [[1], [0, 2]], L, 1, False, nthreads=1)
+    np.testing.assert_allclose(v["post"][0], [Ld.sum()] * 3, rtol=0, atol=1e-12)
+    f = oracle.decode(code, [[0, 1]], L, 1, False, nthreads=1)
+    np.testing.assert_allclose(f["post"][0], [Ld[0] + Ld[1], Ld.sum(), Ld[1] + Ld[2]], rtol=0, atol=1e-12)
+    # the other order: {v0, v2} first sees only channel values
+    w = oracle.decode_vertical(code, [[0, 2], [1]], L, 1, False, nthreads=1)
+    np.testing.assert_allclose(w["post"][0], [Ld[0] + Ld[1], Ld.sum(), Ld[1] + Ld[2]], rtol=0, atol=1e-12)
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_vertical_equals_map_on_trees(seed):
+    rng = np.random.default_rng(300 + seed)
+    n = int(rng.integers(8, 17))
+    code = _code_from_rows(_random_tree(rng, n), n)
+    llr = rng.normal(1.0, 1.5, size=n).astype(np.float32)
+    want = bitmap.map_llr(code.dense(), llr.astype(np.float64))
+    perm = rng.permutation(n)
+    for groups in ([perm[: n // 2], perm[n // 2:]], [[int(x)] for x in perm]):
+        out = oracle.decode_vertical(code, groups, llr[None], max_iter=2 * n, early_stop=False, nthreads=1)
+        np.testing.assert_allclose(out["post"][0], want, rtol=0, atol=1e-9)

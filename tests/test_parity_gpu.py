@@ -367,3 +367,80 @@ def test_every_uniform_degree_variant(dv, dc, n, lanes):
     windows = (4, max(1, code.m // 16), 1)
     g, r = _run_both(code, windows, llr, 12, True, lanes=lanes)
     print((dv, dc, n), "lanes", lanes, compare(g, r))
+
+
+def _vn_windows(n, G):
+    return [np.arange((g * n) // G, ((g + 1) * n) // G, dtype=np.int32) for g in range(G)]
+
+
+@pytest.mark.parametrize("lanes", [1, 2])
+@pytest.mark.parametrize("which", ["sweep_G8", "qc_G12", "n96_singletons", "one_group"])
+def test_vertical_schedule_meets_bar(which, lanes):
+    """The vertical (VN-group) shuffled schedule, the prior art Sec. I
+    contrasts with, on the GPU against the oracle's vertical decoder: the
+    sweep code with 8 contiguous VN groups, the rate-1/2 QC code (checks of
+    degree 6 and 7) with 12, the n=96 code with one VN per group, and one
+    group of every VN (flooding)."""
+    if which == "sweep_G8":
+        rec = W.SWEEP
+        code = W.CODES[rec["code"]]()
+        llr, _ = W.frames(rec, 2, num_frames=96, first_frame=300)
+        vg, it = _vn_windows(code.n, 8), 20
+    elif which == "qc_G12":
+        rec = W.PRECISION
+        code = W.CODES[rec["code"]]()
+        llr, _ = W.frames(rec, 0, num_frames=96, first_frame=40)
+        vg, it = _vn_windows(code.n, 12), 15
+    elif which == "n96_singletons":
+        code = W.code_n96()
+        llr, _ = make_frames(code.n, 64, 2.0, 0.5, seed=97)
+        vg, it = [[v] for v in np.random.default_rng(5).permutation(code.n)], 6
+    else:
+        code = W.code_n96()
+        llr, _ = make_frames(code.n, 64, 2.0, 0.5, seed=98)
+        vg, it = [np.arange(code.n)], 10
+    dcode = nd.Code(code, vn_groups=vg)
+    try:
+        dcode.tune("fp32", lanes)
+        g = gpu_decode(dcode, llr, it, True)
+    finally:
+        dcode.close()
+    r = oracle.decode_vertical_with_sensitivity(code, vg, llr, it, True)
+    print(which, "lanes", lanes, compare(g, r))
+
+
+def test_vertical_schedule_fp16_and_refusals():
+    """FP16 messages meet the 16-bit posterior bound; the HBM tier, BF16
+    messages, four lanes and batches refuse VN groups."""
+    from paper_1202_1060_amd import _native
+    rec = W.SWEEP
+    code = W.CODES[rec["code"]]()
+    llr, _ = W.frames(rec, 3, num_frames=64, first_frame=800)
+    vg = _vn_windows(code.n, 8)
+    dcode = nd.Code(code, vn_groups=vg)
+    try:
+        g = gpu_decode(dcode, llr, 20, True, "fp16")
+        r = oracle.decode_vertical(code, vg, llr, 20, True)
+        ok = r["syn_ok"].astype(bool)
+        assert np.mean(g["hard"][ok] != r["hard"][ok]) < 1e-3
+        x = torch.from_numpy(llr).to("cuda:0")
+        with pytest.raises(nd.LdpcError) as ei:
+            nd.decode(dcode, x, 20, msg="bf16")
+        assert ei.value.code == nd.LDPC_EUNSUPPORTED
+        with pytest.raises(nd.LdpcError) as ei:
+            dcode.tune("fp32", 4)
+            nd.decode(dcode, x, 20)
+        assert ei.value.code == nd.LDPC_EUNSUPPORTED
+        dcode.tune("fp32", 0)
+        out = nd.new_outputs(x.shape[0], code.n, x.device)
+        flags = nd.LDPC_FLAG_EARLY_STOP | _native.LDPC_FLAG_TIER_HBM
+        with pytest.raises(nd.LdpcError) as ei:
+            nd.ldpc_decode(dcode.handle, x.data_ptr(), x.shape[0], 20, flags, out["hard"].data_ptr(),
+                           out["post"].data_ptr(), out["iters"].data_ptr(), out["syn_ok"].data_ptr(),
+                           torch.cuda.current_stream().cuda_stream)
+        assert ei.value.code == nd.LDPC_EUNSUPPORTED
+        with pytest.raises(nd.LdpcError) as ei:
+            nd.Batch([nd.Problem(dcode, x, 20)], msg="fp32")
+        assert ei.value.code == nd.LDPC_EUNSUPPORTED
+    finally:
+        dcode.close()
