@@ -11,9 +11,11 @@ and syndrome flags written back to HBM).
 Prints one JSON line. The decoded info rate counts K = 1152 information bits
 per frame. The roofline object is for the decode kernel, bound by VALU issue
 (26 issue slots per edge update, derived below). Further legs in the same
-line: fixed iterations, FP16 messages, the 256-problem mixed batch against
-one FP32 launch per problem, the HBM tier, and request serving with
-continuous batching (p50/p99 latency) against one FP32 launch per request.
+line: fixed iterations, FP16 messages, the same frames under the baseline
+schedules (flooding BP, disjoint GSBP, vertical GSBP), the 256-problem mixed
+batch against one FP32 launch per problem, the HBM tier, and request serving
+with continuous batching (p50/p99 latency) against one FP32 launch per
+request.
 """
 from __future__ import annotations
 
@@ -371,6 +373,8 @@ def main():
     ap.add_argument("--lanes", type=int, default=0, choices=[0, 1, 2],
                     help="lanes per CN visit for every message format (0: built-in choice)")
     ap.add_argument("--no-batched", action="store_true", help="skip the mixed-batch leg")
+    ap.add_argument("--no-schedules", action="store_true",
+                    help="skip the flooding, GSBP and vertical-GSBP baselines")
     ap.add_argument("--batch-steps", type=int, default=6)
     ap.add_argument("--tune-cache", default=None, help="autotuner cache file (default: user cache dir)")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving leg")
@@ -426,22 +430,22 @@ def main():
                syn_ok=torch.empty((F,), dtype=torch.uint8, device=dev))
     stream = torch.cuda.current_stream(dev)
 
-    def run(steps, early_stop, msg):
+    def run(steps, early_stop, msg, dc):
         evs = []
         for _ in range(steps):
             a = torch.cuda.Event(enable_timing=True)
             b = torch.cuda.Event(enable_timing=True)
             a.record(stream)
-            nd.decode(dcode, llr, rec["max_iter"], early_stop=early_stop, msg=msg, out=out, stream=stream)
+            nd.decode(dc, llr, rec["max_iter"], early_stop=early_stop, msg=msg, out=out, stream=stream)
             b.record(stream)
             evs.append((a, b))
         return evs
 
-    def measure(steps, early_stop, msg):
-        run(args.warmup, early_stop, msg)
+    def measure(steps, early_stop, msg, dc=dcode):
+        run(args.warmup, early_stop, msg, dc)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        evs = run(steps, early_stop, msg)
+        evs = run(steps, early_stop, msg, dc)
         torch.cuda.synchronize()
         wall = (time.perf_counter() - t0) / steps
         kern_ms = float(np.mean([a.elapsed_time(b) for a, b in evs]))
@@ -493,6 +497,24 @@ def main():
         result["fp16_messages"] = {"gbit_s": bits / hwall / 1e9, "kernel_ms": hk,
                                    "lanes_per_cn": dcode.info["lanes_fp16"],
                                    "mean_iters": float(hiters.mean()), "fer": fer_table(hiters, hhard)}
+    if not args.no_schedules:
+        # the same frames under the baseline schedules: flooding BP, GSBP
+        # (8 disjoint CN windows) and vertical GSBP (8 VN windows), FP32
+        sched = {}
+        vn_windows = [np.arange((g * code.n) // 8, ((g + 1) * code.n) // 8, dtype=np.int32) for g in range(8)]
+        for name, kw in (("flooding", dict(windows=(1, 0, 1))), ("gsbp", dict(windows=(8, 0, 1))),
+                         ("vertical_gsbp", dict(vn_groups=vn_windows))):
+            c2 = nd.Code(code, **kw)
+            w2, k2, it2, h2 = measure(max(1, args.steps // 2), True, "fp32", c2)
+            sched[name] = {"gbit_s": bits / w2 / 1e9, "kernel_ms": k2, "mean_iters": float(it2.mean()),
+                           "cn_visits_per_iter": c2.info["cn_visits"],
+                           "edge_updates_per_iter": c2.info["edge_updates"],
+                           "frame_errors": int(sum(r["frame_errors"] for r in fer_table(it2, h2))),
+                           "fer": fer_table(it2, h2)}
+            log(f"schedule {name}: {sched[name]['gbit_s']:.2f} Gbit/s, mean iters {sched[name]['mean_iters']:.2f}, "
+                f"frame errors {sched[name]['frame_errors']}")
+            c2.close()
+        result["schedules"] = sched
     if not args.no_batched:
         result["batched"] = bench_batched(args, torch, nd, W, dev, log)
     if not args.no_hbm:

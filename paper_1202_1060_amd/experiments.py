@@ -10,7 +10,10 @@ The paper compares, on MacKay's (504,252) (3,6) code with G = 12 and on its
   spend the same number of CN updates;
 * NDGSBP with groups that make Step 1's free choices for a large CoCSG
   (``grouping.cocsg_groups``, the open direction of Sec. V), same sizes and
-  budget.
+  budget;
+* vertical group-shuffled BP (the prior art Sec. I cites: G groups of VNs,
+  a random partition), I_max = 1000; every edge message is computed once
+  per iteration, as in BP.
 
 MacKay's matrices are not available; seeded (3,6) n=504 and (4,6) n=816
 codes with the same sizes stand in for them. Frames carry the all-zero
@@ -55,8 +58,9 @@ def clopper_pearson(k, n, alpha=0.05):
 def decoders(code, setup):
     """(name, groups, groups per iteration, iteration cap, CN updates per
     iteration) of the decoders for one code: BP, GSBP, NDGSBP with one
-    Step-1 grouping, and NDGSBP with a fresh Step-1 grouping for every
-    iteration up to its cap (Step 4 returns to Step 1)."""
+    Step-1 grouping, NDGSBP with a fresh Step-1 grouping for every iteration
+    up to its cap (Step 4 returns to Step 1), the same with CoCSG-seeking
+    groupings, and vertical GSBP (VN groups)."""
     M = code.m
     G, r, I = setup["G"], setup["r"], setup["I_max"]
     rng = np.random.Generator(np.random.Philox(setup["seed"]))
@@ -79,7 +83,9 @@ def decoders(code, setup):
             ("gsbp", gs_groups, 0, I, M),
             ("ndgsbp", nd_groups, 0, I_nd, per_iter),
             ("ndgsbp_regroup", sched, G, I_nd, per_iter),
-            ("ndgsbp_cocsg_regroup", sched_l, G, I_nd, per_iter)], \
+            ("ndgsbp_cocsg_regroup", sched_l, G, I_nd, per_iter),
+            ("vgsbp", [np.sort(x).astype(np.int32) for x in np.array_split(rng.permutation(code.n), G)],
+             0, I, M)], \
         dict(N_G=N_G, I_ndgsbp=I_nd, ell_gsbp=cocsg(code, gs_groups)[0], ell_step1=float(np.mean(ell_step1)),
              ell_cocsg=float(np.mean(ell_cocsg)))
 
@@ -99,7 +105,10 @@ def run(code_key, ebn0s, frames, device, log=None, chunk=1 << 18, only=None):
         for name, groups, gpi, cap, cn_per_iter in decs:
             if only and name not in only:
                 continue
-            dcode = Code(code, groups=groups, device=device.index or 0, groups_per_iteration=gpi)
+            if name == "vgsbp":  # VN groups: the vertical schedule
+                dcode = Code(code, vn_groups=groups, device=device.index or 0)
+            else:
+                dcode = Code(code, groups=groups, device=device.index or 0, groups_per_iteration=gpi)
             fe = be = it = 0
             t0 = time.perf_counter()
             done = 0
