@@ -101,7 +101,7 @@ typedef struct {
     int64_t lds_bytes_16;    /* per-frame LDS of the FP16-message kernel      */
     int64_t lds_limit;       /* LDS per workgroup on the device; codes above
                                 it decode in the HBM tier                     */
-    int32_t lanes_fp32;      /* lanes per CN visit used with FP32 messages    */
+    int32_t lanes_fp32;      /* lanes per CN visit (1, 2, 4) with FP32 messages */
     int32_t lanes_fp16;      /* ... with FP16 messages                        */
     int32_t lanes_bf16;      /* ... with BF16 messages                        */
     int32_t groups_per_iteration;

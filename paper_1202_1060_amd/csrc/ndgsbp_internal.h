@@ -24,7 +24,7 @@ constexpr double kLn2 = 0.6931471805599453;
 constexpr double kXMax = 30.0;
 constexpr double kXMin = 1.8715245937680347e-13;
 
-// Table layout (built by ldpc_code_create). H lanes share a CN (1 or 2);
+// Table layout (built by ldpc_code_create). H lanes share a CN (1, 2 or 4);
 // D is the padded CN degree of the kernel variant (a multiple of H, at least
 // the largest degree) and DH = D / H the edges per lane:
 //   vcn[j]         CN of visit j (visits of group g: visit_ptr[g] ..
@@ -36,7 +36,11 @@ constexpr double kXMin = 1.8715245937680347e-13;
 //                  posterior when the VN has no other edge in this group,
 //                  else a delta slot (index >= ds_start) that the fix-up
 //                  pass folds in. Padding edges read and write posterior n,
-//                  a scratch posterior nobody else reads.
+//                  a scratch posterior nobody else reads; with VN groups
+//                  (the vertical schedule) an edge whose VN is outside the
+//                  group reads its VN and writes posterior n.
+//                  The edge order within a row is chosen per CN for LDS
+//                  banks (see edge_order in ndgsbp_host.cpp).
 //   fix[q]         fix-up entry of a group: x = VN | count << 16,
 //                  y = first delta slot (relative to ds_start); a VN's slots
 //                  are consecutive and are added in slot order.
