@@ -373,6 +373,7 @@ def main():
     ap.add_argument("--lanes", type=int, default=0, choices=[0, 1, 2],
                     help="lanes per CN visit for every message format (0: built-in choice)")
     ap.add_argument("--no-batched", action="store_true", help="skip the mixed-batch leg")
+    ap.add_argument("--no-pcie", action="store_true", help="skip the end-to-end (host memory) timing")
     ap.add_argument("--no-schedules", action="store_true",
                     help="skip the flooding, GSBP and vertical-GSBP baselines")
     ap.add_argument("--batch-steps", type=int, default=6)
@@ -491,6 +492,26 @@ def main():
             "gbit_s": bits / fwall / 1e9, "kernel_ms": fk,
             "edge_updates_per_s": fe / (fk * 1e-3),
             "roofline_frac": fe * SLOTS_PER_EDGE_UPDATE / (fk * 1e-3) / PEAK_SLOTS_PER_S}
+    if not args.no_pcie:
+        # end to end from host memory: pinned LLRs in, decode, hard decisions
+        # back to pinned host memory (for context; `value` keeps the inputs
+        # resident in HBM)
+        host_llr = torch.from_numpy(llr_np).pin_memory()
+        host_hard = torch.empty((F, code.n), dtype=torch.uint8).pin_memory()
+        walls = []
+        for rep in range(args.warmup + 3):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            llr.copy_(host_llr, non_blocking=True)
+            nd.decode(dcode, llr, rec["max_iter"], early_stop=True, msg=args.msg, out=out, stream=stream)
+            host_hard.copy_(out["hard"], non_blocking=True)
+            torch.cuda.synchronize()
+            if rep >= args.warmup:
+                walls.append(time.perf_counter() - t0)
+        pw = float(np.median(walls))
+        result["end_to_end_pcie"] = {"gbit_s": bits / pw / 1e9, "ms": pw * 1e3,
+                                     "h2d_bytes": int(llr_np.nbytes), "d2h_bytes": int(F * code.n)}
+        del host_llr, host_hard
     if args.msg == "fp32" and not args.no_fp16:
         # the precision form: FP16-stored messages, FP32 arithmetic, same frames
         hwall, hk, hiters, hhard = measure(args.steps, True, "fp16")
