@@ -46,18 +46,29 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def kernel_sources_key(paths):
+    """sha1 of the kernel sources with comments and white space removed: a
+    comment edit leaves the key (and the device code) as it was, any change
+    to the code gives a new key."""
+    import hashlib
+    import re
+    h = hashlib.sha1()
+    for p in paths:
+        text = open(os.path.join(ROOT, p)).read()
+        text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", " ", text)
+        h.update(" ".join(text.split()).encode())
+    return h.hexdigest()
+
+
 def measured_traffic(msg):
     """HBM bytes per launch from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE
-    record, if it was taken on the kernel sources as they are now (else None)."""
-    import hashlib
+    record, if it was taken on the kernel code as it is now (else None)."""
     path = os.path.join(ROOT, "profiles", "traffic_n2304_sweep.json")
     if msg != "fp32" or not os.path.exists(path):
         return None
     rec = json.load(open(path))
-    h = hashlib.sha1()
-    for p in rec["kernel_sources"]:
-        h.update(open(os.path.join(ROOT, p), "rb").read())
-    if h.hexdigest() != rec["kernel_sources_sha1"]:
+    if kernel_sources_key(rec["kernel_sources"]) != rec["kernel_sources_key"]:
         return None
     return rec["fetch_bytes_per_launch"] + rec["write_bytes_per_launch"]
 
