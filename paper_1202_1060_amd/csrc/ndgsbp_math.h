@@ -55,10 +55,12 @@ __device__ __forceinline__ float exp2_hw(float x) { return __builtin_amdgcn_exp2
 __device__ __forceinline__ float log2_hw(float x) { return __builtin_amdgcn_logf(x); }
 __device__ __forceinline__ float rcp_hw(float x) { return __builtin_amdgcn_rcpf(x); }
 
-// eps = 1 - tanh(|x|/2) = 2v/(1 + v) = 2/(1 + 2^y) for magnitude y (log2
-// units): one exp2, one add, one reciprocal (the factor 2 folds into the
-// (+) that uses it); relative error a few ulp for all y in the clamp range
-__device__ __forceinline__ float eps_from_magnitude(float y) { return 2.0f * rcp_hw(1.0f + exp2_hw(y)); }
+// eps = 1 - tanh(|x|/2) = 2v/(1 + v) = 1/(0.5 + 0.5 * 2^y) for magnitude y
+// (log2 units): one exp2, one fused multiply-add, one reciprocal (halving
+// 1 + 2^y is exact, so this is 2/(1 + 2^y) with the factor 2 moved inside
+// the reciprocal, where it costs nothing); relative error a few ulp for all
+// y in the clamp range
+__device__ __forceinline__ float eps_from_magnitude(float y) { return rcp_hw(fmaf(0.5f, exp2_hw(y), 0.5f)); }
 
 // 1 - (1 - c)(1 - e) in one add and one fused multiply-add
 __device__ __forceinline__ float oplus(float c, float e) { return fmaf(-c, e, c + e); }
