@@ -37,7 +37,7 @@ __device__ __forceinline__ uint32_t quad_half_swap(uint32_t x) {
 // up to rounding) and the fix-up adds the changes of all its edges.
 template <class M, int DH, bool UNI, int H>
 __device__ __forceinline__ void cn_core(const float (&pv)[DH], const float (&lo)[DH], const bool (&real)[DH],
-                                        float ymin, float ymax, float cmin, typename M::T (&st)[DH],
+                                        float ymax, float cmin, typename M::T (&st)[DH],
                                         float (&wv)[DH]) {
     float t[DH], e[DH];
     uint32_t tb[DH];
@@ -47,7 +47,11 @@ __device__ __forceinline__ void cn_core(const float (&pv)[DH], const float (&lo)
         t[k] = pv[k] - lo[k];  // VN->CN message, eq. (2)
         // posteriors never hold -0.0, so the sign bit of t is the sign rule
         tb[k] = __float_as_uint(t[k]);
-        e[k] = eps_from_magnitude(clampf(fabsf(t[k]), ymin, ymax));
+        // |t| is clamped to [0, ymax]: the lower clamp phi(30) of the rule
+        // changes nothing in FP32, where 2^y is 1 for every y below it and
+        // eps is 1 either way; the constant 0 keeps the clamp one instruction
+        // with a single scalar operand
+        e[k] = eps_from_magnitude(clampf(fabsf(t[k]), 0.0f, ymax));
         if (!UNI) {
             e[k] = real[k] ? e[k] : 0.0f;  // 0 is the identity of (+)
             tb[k] = real[k] ? tb[k] : 0u;

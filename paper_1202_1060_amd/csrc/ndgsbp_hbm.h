@@ -22,7 +22,7 @@ struct HbmArgs {
     uint32_t* work;          // this launch's {next frame, finished workgroups}, zero at launch
     int32_t early_stop;
     int32_t packed;
-    float ymin, ymax, cmin;
+    float ymax, cmin;
 };
 
 hipError_t launch_hbm(const HbmArgs& a, MsgKind kind, int D, bool uniform, int blocks, int threads,

@@ -142,7 +142,7 @@ __global__ __launch_bounds__(HbmMaxThreads<D>::value) void ndgsbp_hbm_kernel(Hbm
                     lo[k] = zero_old ? 0.0f : M::unpack(row[k * kSlots]);
                     real[k] = pa[k] != p.pad_b;
                 }
-                cn_core<M, D, UNI, 1>(pv, lo, real, a.ymin, a.ymax, a.cmin, st, wvals);
+                cn_core<M, D, UNI, 1>(pv, lo, real, a.ymax, a.cmin, st, wvals);
 #pragma unroll
                 for (int k = 0; k < D; ++k) {
                     fw[(size_t)ta[k] * (kSlots / 4) + lane] = wvals[k];

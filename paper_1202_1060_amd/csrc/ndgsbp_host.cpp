@@ -398,7 +398,6 @@ void set_launch_constants(DecodeArgs& a, uint32_t flags, size_t lds) {
     a.early_stop = (flags & LDPC_FLAG_EARLY_STOP) ? 1 : 0;
     a.packed = (flags & LDPC_FLAG_OUT_PACKED) ? 1 : 0;
     a.sh_offset = (int32_t)(lds - 16);
-    a.ymin = (float)(kXMin * kLog2e);
     a.ymax = (float)(kXMax * kLog2e);
     a.cmin = (float)kXMin;
 }
@@ -724,7 +723,6 @@ int decode_hbm(ldpc_code* c, const float* llr, int32_t num_frames, int32_t max_i
     a.work = c->dev.work + 2 * (c->next_work.fetch_add(1) % kWorkRing);
     a.early_stop = (flags & LDPC_FLAG_EARLY_STOP) ? 1 : 0;
     a.packed = (flags & LDPC_FLAG_OUT_PACKED) ? 1 : 0;
-    a.ymin = (float)(kXMin * kLog2e);
     a.ymax = (float)(kXMax * kLog2e);
     a.cmin = (float)kXMin;
     if (c->hbm_used) {
@@ -909,6 +907,10 @@ int ldpc_code_create(const ldpc_h_csr* H, const ldpc_grouping* grouping, int32_t
                 vw[half + k % DH] = src;
                 vw[half + DH + k % DH] = dst;
             }
+            // a half-record with a spare word (DH odd) carries the lane's
+            // message row, so that the kernel needs no vcn read for it
+            if (W > 2 * DH)
+                for (int hh = 0; hh < h; ++hh) vw[(j * h + (size_t)hh) * W + 2 * DH] = (uint32_t)(vcn[j] * h + hh);
         }
         const int SD = (D + 3) / 4 * 4;  // syndrome row stride
         std::vector<uint32_t>& syn = syn_h[h - 1];

@@ -20,7 +20,8 @@ constexpr double kLn2 = 0.6931471805599453;
 // of the sign-magnitude rule. phi(30) = 2 atanh(e^-30) = 2 e^-30 to double
 // precision. In complement form the clamp of the phi sum S to [phi(30), 30]
 // is a clamp of c = 1 - e^-S to [1 - e^-phi(30), 1 - e^-30]: the lower bound
-// is phi(30) to double precision, the upper bound rounds to 1 in FP32.
+// is phi(30) to double precision, the upper bound rounds to 1 in FP32. The
+// lower clamp of |x| needs no instruction in FP32 (cn_core).
 constexpr double kXMax = 30.0;
 constexpr double kXMin = 1.8715245937680347e-13;
 
@@ -91,7 +92,7 @@ struct DecodeArgs {
     int32_t early_stop;
     int32_t packed;       // hard decisions packed 8 per byte (LSB first)
     int32_t sh_offset;    // byte offset of the workgroup state (frame, flags, problem)
-    float ymin, ymax;     // clamp of |VN->CN message|, log2 units
+    float ymax;           // upper clamp of |VN->CN message|, log2 units
     float cmin;           // lower clamp of the complement 1 - prod tanh
 };
 

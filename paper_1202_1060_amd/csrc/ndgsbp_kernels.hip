@@ -101,7 +101,9 @@ struct Row {
 template <int DH>
 struct VisitRegs {
     static constexpr int kWords = (2 * DH + 3) / 4 * 4;  // half-record stride in words
-    int cn;
+    // the record's spare word (DH odd) holds the message row cn * H + h
+    static constexpr bool kRowInRecord = kWords > 2 * DH;
+    uint32_t rc;  // that row if kRowInRecord, else the visit's CN
     uint32_t pa[DH];
     uint32_t ta[DH];
 };
@@ -111,9 +113,7 @@ struct VisitRegs {
 template <int DH, int H>
 __device__ __forceinline__ void load_visit(const Problem& p, int j0, int item, int h, VisitRegs<DH>& r) {
     constexpr int W = VisitRegs<DH>::kWords;
-    const unsigned char* cbase = reinterpret_cast<const unsigned char*>(p.vcn) + (size_t)j0 * 4;
     const unsigned char* wbase = reinterpret_cast<const unsigned char*>(p.vw) + (size_t)j0 * (H * W * 4);
-    r.cn = *reinterpret_cast<const int32_t*>(cbase + (uint32_t)item * 4u);
     const uint4* src = reinterpret_cast<const uint4*>(wbase + (uint32_t)(item * H + h) * (uint32_t)(W * 4));
     uint32_t w[W];
 #pragma unroll
@@ -129,6 +129,12 @@ __device__ __forceinline__ void load_visit(const Problem& p, int j0, int item, i
         r.pa[k] = w[k];
         r.ta[k] = w[DH + k];
     }
+    if constexpr (VisitRegs<DH>::kRowInRecord) {
+        r.rc = w[2 * DH];
+    } else {
+        const unsigned char* cbase = reinterpret_cast<const unsigned char*>(p.vcn) + (size_t)j0 * 4;
+        r.rc = (uint32_t) * reinterpret_cast<const int32_t*>(cbase + (uint32_t)item * 4u);
+    }
 }
 
 // One lane's share of a CN visit: eq. (1) for its edges (cn_core), then
@@ -140,7 +146,8 @@ __device__ __forceinline__ void cn_visit(const DecodeArgs& a, const Problem& p, 
                                          uint32_t h) {
     constexpr int DH = D / H;
     using R = Row<M, DH>;
-    const uint32_t row = (uint32_t)p.l_offset + __umul24((uint32_t)(r.cn * H) + h, (uint32_t)R::kBytes);
+    const uint32_t ri = VisitRegs<DH>::kRowInRecord ? r.rc : r.rc * H + h;
+    const uint32_t row = (uint32_t)p.l_offset + __umul24(ri, (uint32_t)R::kBytes);
     float pv[DH], lo[DH], wv[DH];
     bool real[DH];
     typename M::T st[DH];
@@ -150,7 +157,7 @@ __device__ __forceinline__ void cn_visit(const DecodeArgs& a, const Problem& p, 
         pv[k] = lds_f32(r.pa[k]);
         real[k] = r.pa[k] != p.pad_b;
     }
-    cn_core<M, DH, UNI, H>(pv, lo, real, a.ymin, a.ymax, a.cmin, st, wv);
+    cn_core<M, DH, UNI, H>(pv, lo, real, a.ymax, a.cmin, st, wv);
     if constexpr (VERT) {
 #pragma unroll
         for (int k = 0; k < DH; ++k)
