@@ -183,8 +183,9 @@ __global__ __launch_bounds__(HbmMaxThreads<D>::value) void ndgsbp_hbm_kernel(Hbm
             uint32_t x = 0;
             for (int c = wv; c < p.m; c += nw) {
                 uint32_t par = 0;
+                // entries D .. SD - 1 are padding of every row
 #pragma unroll
-                for (int k = 0; k < SD; ++k)
+                for (int k = 0; k < D; ++k)
                     par ^= __float_as_uint(fw[(size_t)tbl_u32(p.syn_col, (uint32_t)c * SD + k) * (kSlots / 4) + lane]);
                 x |= par;
                 if ((__ballot(x >> 31) & need) == need) break;

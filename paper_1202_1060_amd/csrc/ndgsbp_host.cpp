@@ -920,6 +920,7 @@ int ldpc_code_create(const ldpc_h_csr* H, const ldpc_grouping* grouping, int32_t
         // LDS instruction, so 32 consecutive checks are read together: each
         // check of such a run puts its VNs at the free positions whose bank
         // is least used in the run so far (padding reads one shared word).
+        // Positions D .. SD - 1 stay padding: the kernels do not read them.
         {
             const int B = NDGSBP_LDS_BANKS;
             std::vector<int32_t> used((size_t)SD * B);
@@ -927,11 +928,11 @@ int ldpc_code_create(const ldpc_h_csr* H, const ldpc_grouping* grouping, int32_t
                 std::fill(used.begin(), used.end(), 0);
                 for (int i = r0; i < std::min(m, r0 + 32); ++i) {
                     uint32_t* row = &syn[(size_t)i * SD];
-                    std::vector<char> taken(SD, 0);
+                    std::vector<char> taken(D, 0);
                     for (int32_t q = H->row_ptr[i]; q < H->row_ptr[i + 1]; ++q) {
                         const int b = H->col_idx[q] % B;
                         int pick = -1;
-                        for (int k = 0; k < SD; ++k)
+                        for (int k = 0; k < D; ++k)
                             if (!taken[k] && (pick < 0 || used[(size_t)k * B + b] < used[(size_t)pick * B + b])) pick = k;
                         taken[pick] = 1;
                         ++used[(size_t)pick * B + b];

@@ -46,8 +46,9 @@ constexpr double kXMin = 1.8715245937680347e-13;
 //                  y = first delta slot (relative to ds_start); a VN's slots
 //                  are consecutive and are added in slot order.
 //   syn_col        check c at c * SD (SD = D rounded up to 4): 4 x the VN
-//                  ids of the check, padded with 4 x (n + 1) (a posterior
-//                  fixed at +0, i.e. hard bit 0).
+//                  ids of the check within its first D entries, padded with
+//                  4 x (n + 1) (a posterior fixed at +0, i.e. hard bit 0);
+//                  entries D .. SD - 1 are always padding and never read.
 // LDS of a workgroup (one frame):
 //   floats [0, ds_start + max_slots): posteriors (n + 2, ds_start = n + 2)
 //     then delta slots;

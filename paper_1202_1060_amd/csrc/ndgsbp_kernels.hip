@@ -187,9 +187,11 @@ __device__ __forceinline__ void fold_deltas(const Problem& p, uint2 e) {
     lds_f32(4u * v) = acc;
 }
 
-// Syndrome rows (LDS byte offsets of a check's posteriors, padded to SD)
-// that a lane keeps in registers for its first K checks tid, tid + nt, ...;
-// a check past m reads the constant +0 posterior n + 1 only.
+// Syndrome rows (LDS byte offsets of a check's posteriors, stored padded to
+// SD) that a lane keeps in registers for its first K checks tid, tid + nt,
+// ...; a check past m reads the constant +0 posterior n + 1 only. Entries
+// D .. SD - 1 of every row are padding (no check has more than D entries),
+// so they are neither kept nor read.
 // K (measured on the n=2304 workload): one check with two lanes per CN, two
 // with one, none above degree 8; more registers per lane would cut the
 // workgroups resident per CU.
@@ -197,26 +199,29 @@ template <int SD, int H>
 struct SynChecks {
     static constexpr int value = SD > 8 ? 0 : H >= 2 ? 1 : 2;
 };
-template <int SD, int K>
+template <int SD, int D, int K>
 struct SynRows {
-    uint32_t w[K > 0 ? K : 1][SD];
+    uint32_t w[K > 0 ? K : 1][D];
     __device__ __forceinline__ void load(const Problem& p, int tid, int nt) {
 #pragma unroll
         for (int j = 0; j < K; ++j) {
             const int c = tid + j * nt;
             if (c < p.m) {
                 const uint4* col = reinterpret_cast<const uint4*>(p.syn_col + (size_t)c * SD);
+                uint32_t e[SD];
 #pragma unroll
                 for (int q = 0; q < SD / 4; ++q) {
                     const uint4 x = col[q];
-                    w[j][4 * q] = x.x;
-                    w[j][4 * q + 1] = x.y;
-                    w[j][4 * q + 2] = x.z;
-                    w[j][4 * q + 3] = x.w;
+                    e[4 * q] = x.x;
+                    e[4 * q + 1] = x.y;
+                    e[4 * q + 2] = x.z;
+                    e[4 * q + 3] = x.w;
                 }
+#pragma unroll
+                for (int k = 0; k < D; ++k) w[j][k] = e[k];
             } else {
 #pragma unroll
-                for (int k = 0; k < SD; ++k) w[j][k] = 4u * (uint32_t)(p.n + 1);
+                for (int k = 0; k < D; ++k) w[j][k] = 4u * (uint32_t)(p.n + 1);
             }
         }
     }
@@ -356,7 +361,7 @@ __global__ __launch_bounds__(MaxThreads<D>::value) void ndgsbp_kernel(DecodeArgs
     bool have_nxt = vitem < table_i32(p.visit_ptr, 1);
     if (have_nxt) load_visit<DH, H>(p, 0, vitem, lh, nxt);
     // rows of this lane's first SYNK checks, kept for the whole decode
-    SynRows<SD, SYNK> srow;
+    SynRows<SD, D, SYNK> srow;
     srow.load(p, tid, nt);
     __syncthreads();
 
@@ -409,7 +414,7 @@ __global__ __launch_bounds__(MaxThreads<D>::value) void ndgsbp_kernel(DecodeArgs
             for (int j = 0; j < SYNK; ++j) {
                 uint32_t par = 0;
 #pragma unroll
-                for (int k = 0; k < SD; ++k) par ^= __float_as_uint(lds_f32(srow.w[j][k]));
+                for (int k = 0; k < D; ++k) par ^= __float_as_uint(lds_f32(srow.w[j][k]));
                 x |= par;
             }
             if (x >> 31) lds_i32(fl) = 1;
@@ -417,13 +422,18 @@ __global__ __launch_bounds__(MaxThreads<D>::value) void ndgsbp_kernel(DecodeArgs
         for (int c = tid + SYNK * nt; c < p.m; c += nt) {
             if (lds_i32(fl)) break;
             const uint4* col = reinterpret_cast<const uint4*>(p.syn_col + (size_t)c * SD);
-            uint32_t x = 0;
+            uint32_t e[SD];
 #pragma unroll
             for (int q = 0; q < SD / 4; ++q) {
                 const uint4 w = col[q];
-                x ^= __float_as_uint(lds_f32(w.x)) ^ __float_as_uint(lds_f32(w.y)) ^
-                     __float_as_uint(lds_f32(w.z)) ^ __float_as_uint(lds_f32(w.w));
+                e[4 * q] = w.x;
+                e[4 * q + 1] = w.y;
+                e[4 * q + 2] = w.z;
+                e[4 * q + 3] = w.w;
             }
+            uint32_t x = 0;
+#pragma unroll
+            for (int k = 0; k < D; ++k) x ^= __float_as_uint(lds_f32(e[k]));
             if (x >> 31) lds_i32(fl) = 1;
         }
         __syncthreads();
