@@ -127,7 +127,8 @@ int ldpc_code_query(ldpc_code_t code, ldpc_code_info* info);
  * format in msg_flags (0, LDPC_FLAG_MSG_FP16 or LDPC_FLAG_MSG_BF16): one lane
  * per CN visit (1), or two or four lanes sharing it (2, 4; the padded degree
  * is then a multiple of the lane count); 0 restores the built-in choice
- * (never 4). For tuners: the mappings compute eq. (1) with the same operations
+ * (made at create from the device's LDS size and the occupancy of each
+ * mapping's kernel, per message format; any of 1, 2, 4). For tuners: the mappings compute eq. (1) with the same operations
  * in a different summation order, so results agree up to float rounding.
  * Not synchronised with decodes in flight on other threads.
  * Errors: EINVAL (bad flags or value), EUNSUPPORTED (no kernel variant

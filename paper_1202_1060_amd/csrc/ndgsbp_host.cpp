@@ -220,9 +220,9 @@ int pick_degree(int d, int h) {
 // Lanes per CN visit that a mapping may use.
 bool valid_lanes(int h) { return h == 1 || h == 2 || h == 4; }
 
-// Lanes per CN visit for a message format: the mapping that wastes the fewest
-// lane-edge slots in the CN phase (idle lanes of the last wave plus padding
-// edges), two lanes on a tie; ldpc_code_tune overrides it.
+// Lanes per CN visit before the device is known: the mapping that wastes the
+// fewest lane-edge slots in the CN phase (idle lanes of the last wave plus
+// padding edges), two lanes on a tie; ldpc_code_tune overrides it.
 int pick_lanes(const ldpc_code* c, int max_visits, int64_t max_edges) {
     double best_eff = -1.0;
     int best = 1;
@@ -237,6 +237,51 @@ int pick_lanes(const ldpc_code* c, int max_visits, int64_t max_edges) {
         }
     }
     return best;
+}
+
+// The same choice once the device is known, per message format, among the
+// mappings whose frame fits in LDS. Each lane of a visit pays a fixed cost
+// besides its edges (DPP exchanges, row address), counted as half an edge
+// with four lanes; a mapping is scored by its edges per paid lane-edge slot
+// (all passes of a group counted) times its residency, min(1, waves per
+// SIMD / 4): with fewer waves the CN phase waits on LDS round trips and
+// barriers instead of issuing. When every mapping leaves one workgroup per
+// CU, each barrier idles the CU and the mapping with the widest workgroup
+// is taken whatever its padding (measured faster on codes of n = 4608 and
+// 8064). Two lanes on a tie; 0 when no mapping fits in LDS (the HBM tier
+// decodes such codes).
+int pick_lanes_resident(const ldpc_code* c, MsgKind kind, int64_t max_edges) {
+    constexpr double kWavesToHide = 4.0;
+    double best_score = -1.0;
+    int best = 0, widest = 0, widest_threads = 0;
+    bool all_alone = true;
+    for (int h : {2, 1, 4}) {
+        const Layout& l = c->lay[h - 1];
+        if (!l.valid || (c->vertical && h > 2)) continue;
+        const size_t lds = lds_bytes(c, l, kind);
+        if (lds > c->max_lds) continue;
+        const int threads = threads_for(c, l);
+        int per_cu = 0;
+        if (decode_occupancy(kind, l.D, l.uniform, h, c->vertical ? 2 : 0, threads, lds, &per_cu) != hipSuccess ||
+            per_cu < 1)
+            continue;
+        const int64_t lane_visits = (int64_t)h * c->max_group_visits;
+        const int64_t passes = (lane_visits + threads - 1) / threads;
+        const double fixed = h == 4 ? 0.5 : 0.0;
+        const double eff = (double)max_edges / ((double)passes * threads * (l.D / h + fixed));
+        const double waves = (double)per_cu * (threads / 64) / 4.0;
+        const double score = eff * std::min(1.0, waves / kWavesToHide);
+        if (score > best_score + 1e-9) {
+            best_score = score;
+            best = h;
+        }
+        if (per_cu > 1) all_alone = false;
+        if (threads > widest_threads) {
+            widest_threads = threads;
+            widest = h;
+        }
+    }
+    return best && all_alone ? widest : best;
 }
 
 #ifndef NDGSBP_LDS_BANKS
@@ -942,9 +987,9 @@ int ldpc_code_create(const ldpc_h_csr* H, const ldpc_grouping* grouping, int32_t
             }
         }
     }
-    // FP32 messages: the slot-count choice. 16-bit messages: one lane per
-    // visit, which measured faster than two on the (3,6)-regular n=2304
-    // workload (12.0 against 11.2 Gbit/s) although it idles more lanes.
+    // Provisional mappings until the device's LDS and occupancy are known
+    // (pick_lanes_resident below): FP32 the slot-count choice, 16-bit one
+    // lane per visit.
     const int lanes0 = pick_lanes(c, c->max_group_visits, max_edges);
     const int lanes16 = c->lay[0].valid ? 1 : lanes0;
     c->lanes_for[kMsgF32] = c->lanes_default[kMsgF32] = lanes0;
@@ -986,6 +1031,12 @@ int ldpc_code_create(const ldpc_h_csr* H, const ldpc_grouping* grouping, int32_t
         c->max_lds = (size_t)v;
     }
     if (e == hipSuccess) e = hipDeviceGetAttribute(&c->num_cus, hipDeviceAttributeMultiprocessorCount, device);
+    if (e == hipSuccess) {
+        for (MsgKind k : {kMsgF32, kMsgF16, kMsgBF16}) {
+            const int h = pick_lanes_resident(c, k, max_edges);
+            if (h) c->lanes_for[k] = c->lanes_default[k] = h;
+        }
+    }
     if (e != hipSuccess) {
         free_tables(c);
         delete c;
