@@ -168,21 +168,22 @@ __device__ __forceinline__ void cn_visit(const DecodeArgs& a, const Problem& p, 
     R::store(row, st);
 }
 
-// Fix-up of one VN with c edges in the group: its posterior P plus the
-// change w - P of each of its edges (w: the posterior that edge alone would
-// leave, in its slot), added in slot order. The first four slots are loaded
-// together (reads past the VN's slots land in the LDS allocation and are
-// unused).
+// Fix-up of one VN with c >= 2 edges in the group (a VN with one edge has
+// no entry): its posterior P plus the change w - P of each of its edges (w:
+// the posterior that edge alone would leave, in its slot), added in slot
+// order. The first four slots are loaded together (reads past the VN's
+// slots land in the LDS allocation and are unused).
 __device__ __forceinline__ void fold_deltas(const Problem& p, uint2 e) {
     const uint32_t v = e.x & 0xffffu, c = e.x >> 16;
     const uint32_t d0 = p.ds_start_b + 4u * e.y;
     const float p0 = lds_f32(4u * v);
-    float acc = p0;
     float d[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) d[k] = lds_f32(d0 + 4u * k);
+    float acc = p0 + (d[0] - p0);
+    acc += d[1] - p0;
 #pragma unroll
-    for (int k = 0; k < 4; ++k) acc = (uint32_t)k < c ? acc + (d[k] - p0) : acc;
+    for (int k = 2; k < 4; ++k) acc = (uint32_t)k < c ? acc + (d[k] - p0) : acc;
     for (uint32_t k = 4; k < c; ++k) acc += lds_f32(d0 + 4u * k) - p0;
     lds_f32(4u * v) = acc;
 }
