@@ -211,6 +211,31 @@ def test_repeated_launches_reuse_work_counters():
         assert np.array_equal(out[k].cpu().numpy(), first[k]), k
 
 
+def test_default_mapping_rule():
+    """The built-in CN-lane mapping, chosen at create per message format
+    from LDS residency: two lanes for the (3,6) n=2304 code (FP32), four
+    (the widest workgroup) for the serving workload's QC n=8064 rate-1/2 code
+    with FP32 messages, where every mapping leaves one workgroup per CU; the chosen mapping fits in
+    LDS whenever one does, and tuning to 0 restores it."""
+    sweep = nd.Code(W.CODES["n2304"](), windows=(8, 16, 1))
+    big = nd.Code(W.CODES[W.qc_key(8064, "1/2")](), windows=W.serve_windows(8064, "1/2"))
+    try:
+        assert sweep.info["lanes_fp32"] == 2
+        assert big.info["lanes_fp32"] == 4
+        for c in (sweep, big):
+            info = c.info
+            assert info["lds_bytes_fp32"] <= info["lds_limit"] and info["lds_bytes_16"] <= info["lds_limit"]
+            for msg in ("fp32", "fp16", "bf16"):
+                base = info["lanes_" + msg]
+                assert base in (1, 2, 4)
+                c.tune(msg, 1)
+                c.tune(msg, 0)
+                assert c.info["lanes_" + msg] == base
+    finally:
+        sweep.close()
+        big.close()
+
+
 def test_tune_arguments():
     """ldpc_code_tune: bad values and unbuilt mappings are errors; 0
     restores the default; each message format keeps its own choice."""
