@@ -381,7 +381,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fixed", action="store_true", help="skip the fixed-iteration pass")
     ap.add_argument("--no-fp16", action="store_true", help="skip the FP16-message pass")
-    ap.add_argument("--lanes", type=int, default=0, choices=[0, 1, 2],
+    ap.add_argument("--lanes", type=int, default=0, choices=[0, 1, 2, 4],
                     help="lanes per CN visit for every message format (0: built-in choice)")
     ap.add_argument("--no-batched", action="store_true", help="skip the mixed-batch leg")
     ap.add_argument("--no-pcie", action="store_true", help="skip the end-to-end (host memory) timing")
