@@ -54,6 +54,14 @@ def _store(path, db):
     os.replace(tmp, path)
 
 
+def _device_sig(dev) -> list:
+    """Identity of the device kind a tuning result holds for: the ISA, the
+    CU count and the memory size (the marketing name can be empty, e.g.
+    under a profiler)."""
+    pr = torch.cuda.get_device_properties(dev)
+    return [getattr(pr, "gcnArchName", ""), pr.multi_processor_count, pr.total_memory]
+
+
 def _code_sig(code: Code):
     i = code.info
     return (i["m"], i["n"], i["nnz"], i["num_groups"], i["cn_visits"], i["edge_updates"],
@@ -63,7 +71,7 @@ def _code_sig(code: Code):
 def batch_signature(problems, msg: str, early_stop: bool) -> str:
     items = sorted((_code_sig(p.code), int(p.llr.shape[0]).bit_length(), p.max_iter) for p in problems)
     dev = problems[0].llr.device if problems else torch.device("cuda", 0)
-    blob = json.dumps([items, msg, bool(early_stop), torch.cuda.get_device_name(dev)])
+    blob = json.dumps([items, msg, bool(early_stop), _device_sig(dev)])
     return "batch:" + hashlib.sha1(blob.encode()).hexdigest()
 
 
@@ -188,7 +196,7 @@ def tune_code(code: Code, llr: torch.Tensor, max_iter: int, *, msg: str = "fp32"
     frames ``llr``, apply it (ldpc_code_tune) and return it."""
     path = _cache_path(cache)
     blob = json.dumps([_code_sig(code), int(llr.shape[0]).bit_length(), max_iter, msg, bool(early_stop),
-                       torch.cuda.get_device_name(llr.device)])
+                       _device_sig(llr.device)])
     key = "code:" + hashlib.sha1(blob.encode()).hexdigest()
     db = _load(path)
     if not force and key in db:
