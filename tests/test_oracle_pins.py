@@ -85,6 +85,55 @@ def test_fig1_grouping_is_windows():
     assert G * NG - (G - 1) * NG * r == 4
 
 
+def _check_wrapped_windows(w, M, G, o, length):
+    """The wraparound grouping as the workloads state it: G windows of
+    `length` CNs, consecutive windows (the last and the first included)
+    sharing exactly o CNs, the shared CNs being the tail of one window and
+    the head of the next, every CN covered, M + G*o CN updates in all."""
+    assert len(w) == G
+    assert all(len(x) == length for x in w)
+    assert sum(len(x) for x in w) == M + G * o
+    assert set(np.concatenate(w).tolist()) == set(range(M))
+    for g in range(G):
+        a, b = list(w[g]), list(w[(g + 1) % G])
+        assert len(set(a) & set(b)) == o, (g, set(a) & set(b))
+        assert a[len(a) - o:] == b[:o]
+        assert len(set(a)) == len(a)
+
+
+def test_wrapped_windows_of_the_small_workload():
+    # n=96 (3,6) code, m=48: 4 windows of 14 CNs with a 2-CN overlap, wrap
+    w = oracle.windows(48, 4, 2, wrap=True)
+    _check_wrapped_windows(w, 48, 4, 2, 14)
+    want = [list(range(0, 14)), list(range(12, 26)), list(range(24, 38)), list(range(36, 48)) + [0, 1]]
+    assert [list(x) for x in w] == want
+
+
+def test_wrapped_windows_of_the_sweep_workload():
+    # n=2304 (3,6) code, m=1152: 8 windows of 160 CNs with a 16-CN overlap, wrap
+    w = oracle.windows(1152, 8, 16, wrap=True)
+    _check_wrapped_windows(w, 1152, 8, 16, 160)
+    for g in range(7):
+        assert list(w[g]) == list(range(144 * g, 144 * g + 160))
+    assert list(w[7]) == list(range(1008, 1152)) + list(range(16))
+
+
+def test_windows_uneven_split_by_hand():
+    # M=10, G=3, overlap 1: starts floor(0)=0, floor(10/3)=3, floor(20/3)=6
+    assert [list(x) for x in oracle.windows(10, 3, 1, wrap=True)] == \
+        [[0, 1, 2, 3], [3, 4, 5, 6], [6, 7, 8, 9, 0]]
+    # without wrap the last window stops at M (G-1 overlaps, as in Fig. 1)
+    assert [list(x) for x in oracle.windows(10, 3, 1, wrap=False)] == \
+        [[0, 1, 2, 3], [3, 4, 5, 6], [6, 7, 8, 9]]
+    # zero overlap partitions the CNs (the disjoint GSBP baseline)
+    assert [list(x) for x in oracle.windows(10, 3, 0, wrap=True)] == \
+        [[0, 1, 2], [3, 4, 5], [6, 7, 8, 9]]
+    # one window holding every CN (flooding)
+    assert [list(x) for x in oracle.windows(10, 1, 0, wrap=True)] == [list(range(10))]
+    with pytest.raises(ValueError):
+        oracle.windows(10, 2, 6, wrap=True)
+
+
 # ------------------------------------------------------------- MAP on trees
 
 def _random_tree(rng, n_vn, max_dc=4):
