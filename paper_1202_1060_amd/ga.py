@@ -29,7 +29,8 @@ Q(sqrt(mu_total/2)), falling below 1e-6; iterations are counted from 1.
   G). With r = 0 this reproduces the paper's GSBP columns of Table I
   exactly for both ensembles (293, 262, 251 and 438, 386, 376); the r = 0.4
   columns come within 1-4% (240, 211, 203 against 240, 208, 196; 373, 335,
-  331 against 368, 324, 317).
+  331 against 368, 324, 317): parity unpinned for r > 0, the values are
+  reported beside the table, not held to it.
 """
 from __future__ import annotations
 
