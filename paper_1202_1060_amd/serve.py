@@ -15,7 +15,8 @@ of one code. Two policies share the request bookkeeping:
   stream, with FP32 messages (the reference policy).
 
 Memory: an admitted request holds its outputs (hard decisions, iteration
-count, syndrome flag) in device memory until its launch completes; the
+count, syndrome flag, and with ``posteriors`` the total LLRs) in device
+memory until its launch completes; the
 budget caps the bytes held by requests in flight. Request LLRs are device
 buffers owned by the caller (the request's ``llr`` address); code tables
 and message state stay on the device (messages live in LDS for the whole
@@ -62,7 +63,7 @@ class Requests:
 
 class Server:
     def __init__(self, codes, *, policy="batched", msg="fp16", early_stop=True, budget_bytes=1 << 30,
-                 max_inflight=4, device=0):
+                 max_inflight=4, device=0, posteriors=False):
         if policy not in ("batched", "plain"):
             raise ValueError(policy)
         self.codes = list(codes)
@@ -77,9 +78,13 @@ class Server:
         nstreams = max_inflight if policy == "batched" else 1
         self.streams = [torch.cuda.Stream(self.device) for _ in range(nstreams)]
         self.lib = _native.load()
+        self.posteriors = bool(posteriors)
 
     def request_bytes(self, req: Requests):
-        return req.frames * (self.n[req.code] + 4 + 1)
+        """Device bytes a request holds while in flight: its outputs (hard
+        decisions, iteration count, syndrome flag, and posteriors if kept)."""
+        per_bit = 5 if self.posteriors else 1
+        return req.frames * (self.n[req.code] * per_bit + 4 + 1)
 
     def run(self, req: Requests, *, keep_results=False, clock=time.perf_counter):
         """Serve the stream in real time; returns per-request arrays
@@ -154,6 +159,8 @@ class Server:
             hard = torch.empty(int(hard_off[-1]), dtype=torch.uint8, device=self.device)
             iters = torch.empty(int(it_off[-1]), dtype=torch.int32, device=self.device)
             syn = torch.empty(int(it_off[-1]), dtype=torch.uint8, device=self.device)
+            post = torch.empty(int(hard_off[-1]), dtype=torch.float32, device=self.device) \
+                if self.posteriors else None
         probs = np.zeros(b - a, dtype=PROBLEM_DTYPE)
         probs["code"] = self.handles[req.code[a:b]]
         probs["llr"] = req.llr_addr[a:b]
@@ -162,11 +169,14 @@ class Server:
         probs["hard"] = np.uint64(hard.data_ptr()) + hard_off[:-1].astype(np.uint64)
         probs["iters"] = np.uint64(iters.data_ptr()) + (4 * it_off[:-1]).astype(np.uint64)
         probs["syn_ok"] = np.uint64(syn.data_ptr()) + it_off[:-1].astype(np.uint64)
+        if post is not None:
+            probs["post"] = np.uint64(post.data_ptr()) + (4 * hard_off[:-1]).astype(np.uint64)
         if self.policy == "plain":
             p = probs[0]
             rc = self.lib.ldpc_decode(ctypes.c_void_p(int(p["code"])), ctypes.c_void_p(int(p["llr"])),
                                       int(p["num_frames"]), int(p["max_iter"]), self.flags,
-                                      ctypes.c_void_p(int(p["hard"])), None, ctypes.c_void_p(int(p["iters"])),
+                                      ctypes.c_void_p(int(p["hard"])), ctypes.c_void_p(int(p["post"]) or None),
+                                      ctypes.c_void_p(int(p["iters"])),
                                       ctypes.c_void_p(int(p["syn_ok"])), ctypes.c_void_p(stream.cuda_stream))
         else:
             rc = self.lib.ldpc_decode_batched(probs.ctypes.data_as(ctypes.POINTER(_native.ldpc_problem)),
@@ -174,16 +184,19 @@ class Server:
         _native.check(rc)
         ev = torch.cuda.Event()
         ev.record(stream)
-        return ev, (hard, iters, syn, hard_off, it_off, n)
+        return ev, (hard, iters, syn, post, hard_off, it_off, n)
 
     @staticmethod
     def _keep(results, req, a, b, bufs):
-        hard, iters, syn, hard_off, it_off, n = bufs
+        hard, iters, syn, post, hard_off, it_off, n = bufs
         h, it, sy = hard.cpu().numpy(), iters.cpu().numpy(), syn.cpu().numpy()
+        po = post.cpu().numpy() if post is not None else None
         for j in range(b - a):
             F = int(req.frames[a + j])
             results[a + j] = dict(hard=h[hard_off[j]:hard_off[j + 1]].reshape(F, int(n[j])),
                                   iters=it[it_off[j]:it_off[j + 1]], syn_ok=sy[it_off[j]:it_off[j + 1]])
+            if po is not None:
+                results[a + j]["post"] = po[hard_off[j]:hard_off[j + 1]].reshape(F, int(n[j]))
 
 
 __all__ = ["Server", "Requests", "PROBLEM_DTYPE"]

@@ -3,23 +3,35 @@ the FP64 oracle.
 
 Bar for FP32 messages, per frame, using the oracle's own conditioning
 ``sens`` (largest posterior change of the FP64 decode when every input LLR
-moves by one float32 ulp; see oracle.decode_with_sensitivity):
+moves by one float32 ulp, inf when that changes a decision or the iteration
+count; see oracle.decode_with_sensitivity):
 
-* well-conditioned frames (decoded by the oracle and sens < SENS_WELL):
-  hard decisions, iteration
-  count and syndrome flag identical; every posterior within
-  ATOL + RTOL |ref| (1e-3 absolute near zero, 1e-4 relative);
-* ill-conditioned frames: the posterior tolerance widens by K_SENS * sens,
-  because FP32 rounding at every message update is amplified the way the
-  one-ulp input change is; frames the oracle decodes must still give
-  identical decisions, and wherever the decisions match the syndrome flag
-  and iteration count must match too; on frames the oracle does not decode
-  decision differences are counted and capped at 2% of those frames, not
-  counting frames whose FP64 decisions themselves change under a one-ulp
-  input change (such a chaotic frame may end decoded on the GPU, with its
-  own flag and count).
-Across all frames hard decisions must match on >= 99.99%, or every
-mismatch must sit in an undecoded, ill-conditioned frame.
+* frames the oracle decodes: identical hard decisions (no exception);
+* wherever the decisions match: identical syndrome flag and iteration count;
+* well-conditioned frames (decoded, sens < SENS_WELL): every posterior
+  within ATOL + RTOL |ref| (1e-3 absolute near zero, 1e-4 relative);
+* other frames with matching decisions: the posterior bound widens by
+  K_SENS * sens: FP32 rounds every message update, a perturbation that the
+  frame amplifies as it amplifies the one-ulp input change. K_SENS = 16 is
+  set from the full-scale record of the n=2304 sweep (7 x 16384 frames),
+  where the largest excess over the strict bound was 9.3 x sens;
+* frame fraction: decisions differ on at most 0.01% of the frames, rounded
+  up to a whole frame, not counting frames the oracle leaves undecoded
+  whose FP64 decisions themselves change under the one-ulp input change
+  (chaotic: no float32 decoder is bound to follow FP64 there, and such a
+  frame may even end decoded on the GPU). ``pooled=True`` leaves this
+  fraction to the caller, who checks it over a whole workload (the
+  full-scale test: >= 99.99% over all 114688 frames of the sweep).
+
+Bar for 16-bit messages (FP16 storage, FP32 arithmetic; compare16):
+hard decisions identical on every frame the oracle decodes; on frames both
+decode, identical iteration counts and every posterior within
+K16 * U16 * (|ref| + 30) nats: U16 = 2^-11 is the unit roundoff of binary16,
+and a stored message (at most 30 nats) is off by at most 30 U16; the error
+a posterior collects from its stored messages over the iterations is
+bounded in the test by K16 = 64 such units plus the relative part. On the
+measured workloads (sweep, QC n=2304 and the three serving codes, 1.0 to
+2.5 dB) the largest error was 26 units.
 """
 from __future__ import annotations
 
@@ -30,6 +42,9 @@ ATOL = 1e-3
 SENS_WELL = 1e-4
 K_SENS = 16.0
 MIN_FRAME_MATCH = 0.9999
+U16 = 2.0 ** -11
+K16 = 64.0
+XMAX_NATS = 30.0
 
 
 def gpu_decode(dcode, llr_np, max_iter, early_stop, msg="fp32", device="cuda:0"):
@@ -41,7 +56,7 @@ def gpu_decode(dcode, llr_np, max_iter, early_stop, msg="fp32", device="cuda:0")
     return {k: v.cpu().numpy() for k, v in out.items() if v is not None}
 
 
-def compare(gpu, ref, rtol=RTOL, atol=ATOL, k_sens=K_SENS):
+def compare(gpu, ref, rtol=RTOL, atol=ATOL, k_sens=K_SENS, pooled=False):
     """``ref`` comes from oracle.decode_with_sensitivity. Returns stats;
     raises AssertionError when the bar is missed."""
     F = ref["hard"].shape[0]
@@ -74,17 +89,37 @@ def compare(gpu, ref, rtol=RTOL, atol=ATOL, k_sens=K_SENS):
     assert np.array_equal(gpu["iters"][match], ref["iters"][match]), "iteration counts differ"
     # posteriors of every frame with matching decisions, widened where ill-conditioned
     assert np.all(pok[match]), f"posteriors out of the widened bound on {int((match & ~pok).sum())} frames"
-    # undecoded frames: a decision difference counts against the cap unless
-    # the FP64 oracle's own decisions on that frame change under a one-ulp
-    # input change (sens = inf): there the result is not determined at the
-    # precision of the float32 input, and no float32 decoder can match it
-    # (such a frame may even end decoded, its flag and count then differ)
+    # the frame fraction: >= 99.99% matching, or every mismatch undecoded
+    # and chaotic (FP64's own decisions change under a one-ulp input change)
     nc = ~conv
     chaotic = ~np.isfinite(sens)
-    nc_mis = int((~match & nc & ~chaotic).sum())
     stats["undecoded_mismatch_chaotic"] = int((~match & nc & chaotic).sum())
-    assert match.sum() >= MIN_FRAME_MATCH * F or nc_mis <= max(1, int(0.02 * nc.sum())), \
-        f"decisions match on {int(match.sum())}/{F} frames ({nc_mis} undecoded, oracle-stable)"
+    stats["undecoded_mismatch_stable"] = int((~match & nc & ~chaotic).sum())
+    stats["control_flips"] = int(chaotic.sum())
+    if not pooled:
+        allowed = int(np.ceil((1.0 - MIN_FRAME_MATCH) * F - 1e-9))
+        assert stats["undecoded_mismatch_stable"] <= allowed, \
+            f"decisions differ on {stats['undecoded_mismatch_stable']} of {F} frames that are not chaotic " \
+            f"(at most {allowed})"
+    return stats
+
+
+def compare16(gpu, ref, k16=K16):
+    """The 16-bit message bar against ``ref`` from oracle.decode (FP64).
+    Returns stats; raises AssertionError when the bar is missed."""
+    conv = ref["syn_ok"] == 1
+    both = conv & (gpu["syn_ok"] == 1)
+    match = np.all(gpu["hard"] == ref["hard"], axis=1)
+    err = np.abs(gpu["post"].astype(np.float64) - ref["post"])
+    units = err / (U16 * (np.abs(ref["post"]) + XMAX_NATS))
+    stats = dict(frames=len(conv), oracle_decoded=int(conv.sum()), both_decoded=int(both.sum()),
+                 decision_mismatch=int((~match).sum()),
+                 max_units=float(units[both].max()) if both.any() else 0.0,
+                 max_abs_err=float(err[both].max()) if both.any() else 0.0)
+    assert np.all(match[conv]), f"decisions differ on {int((~match & conv).sum())} decoded frames"
+    assert np.array_equal(gpu["iters"][both], ref["iters"][both]), \
+        f"iteration counts differ on {int((gpu['iters'][both] != ref['iters'][both]).sum())} decoded frames"
+    assert stats["max_units"] <= k16, f"posterior error {stats['max_units']:.1f} units of U16 (|ref| + 30)"
     return stats
 
 

@@ -13,7 +13,7 @@ import paper_1202_1060_amd as nd  # noqa: E402
 from ldpcgen import Code, regular_code, make_frames  # noqa: E402
 from ldpcgen import workloads as W  # noqa: E402
 
-from parity import gpu_decode, compare  # noqa: E402
+from parity import gpu_decode, compare, compare16  # noqa: E402
 
 
 def _groups(code, windows):
@@ -171,15 +171,29 @@ def test_zero_and_one_frame():
 
 
 def test_largest_code_in_lds_and_one_beyond():
-    # n = 8064 QC rate-1/2 code (z = 336) fits one frame in LDS with FP16 messages
-    code = W.code_qc(8064, "1/2", 1100)
-    dcode = nd.Code(code, windows=(12, 84, 1))
+    # n = 8064 QC rate-1/2 code of the serving workload (z = 336, one base
+    # row per window, overlap 84): FP32 messages with the default four lanes
+    # per CN visit need more lanes per group than a workgroup has, so every
+    # group runs in several passes; FP16 messages with their default mapping
+    key = W.qc_key(8064, "1/2")
+    code = W.CODES[key]()
+    win = W.serve_windows(8064, "1/2")
+    dcode = nd.Code(code, windows=win)
     info = dcode.info
-    assert info["lds_bytes_16"] <= info["lds_limit"]
-    llr, _ = make_frames(code.n, 16, 2.0, 0.5, seed=33)
-    g = gpu_decode(dcode, llr, 10, True, msg="fp16")
-    assert g["iters"].min() >= 1
-    dcode.close()
+    assert info["lds_bytes_16"] <= info["lds_limit"] and info["lds_bytes_fp32"] <= info["lds_limit"]
+    assert info["lanes_fp32"] == 4 and info["cn_visits"] // info["num_groups"] * 4 > 1024
+    groups = _groups(code, win)
+    enc = W.encoder_for(key)
+    try:
+        for eb, seed in ((1.5, 33), (2.5, 34)):
+            llr, _ = make_frames(code.n, 64, eb, enc.rate, seed, encoder=enc)
+            g = gpu_decode(dcode, llr, 20, True)
+            r = oracle.decode_with_sensitivity(code, groups, llr, 20, True)
+            print("n=8064 fp32", eb, compare(g, r))
+            g16 = gpu_decode(dcode, llr, 20, True, msg="fp16")
+            print("n=8064 fp16", eb, compare16(g16, r))
+    finally:
+        dcode.close()
     print("lds per frame (fp32, 16-bit):", info["lds_bytes_fp32"], info["lds_bytes_16"])
     # n = 60000 (near the largest n the tables address): the posteriors alone
     # exceed the LDS of a workgroup, so the decode takes the HBM tier; it must
@@ -284,8 +298,7 @@ def test_lanes_per_check_node(lanes, msg):
             finally:
                 dcode.close()
             r = oracle.decode(code, _groups(code, rec["windows"]), llr, rec["max_iter"], True)
-            ok = r["syn_ok"].astype(bool)
-            assert np.mean(g["hard"][ok] != r["hard"][ok]) < 1e-3
+            print("lanes", lanes, rec["name"], "fp16", compare16(g, r))
             continue
         g, r = _run_both(code, rec["windows"], llr, rec["max_iter"], True, lanes=lanes)
         print("lanes", lanes, rec["name"], compare(g, r))
@@ -435,7 +448,7 @@ def test_vertical_schedule_meets_bar(which, lanes):
 
 
 def test_vertical_schedule_fp16_and_refusals():
-    """FP16 messages meet the 16-bit posterior bound; the HBM tier, BF16
+    """FP16 messages meet the 16-bit bar; the HBM tier, BF16
     messages, four lanes and batches refuse VN groups."""
     from paper_1202_1060_amd import _native
     rec = W.SWEEP
@@ -446,8 +459,7 @@ def test_vertical_schedule_fp16_and_refusals():
     try:
         g = gpu_decode(dcode, llr, 20, True, "fp16")
         r = oracle.decode_vertical(code, vg, llr, 20, True)
-        ok = r["syn_ok"].astype(bool)
-        assert np.mean(g["hard"][ok] != r["hard"][ok]) < 1e-3
+        print("vertical fp16", compare16(g, r))
         x = torch.from_numpy(llr).to("cuda:0")
         with pytest.raises(nd.LdpcError) as ei:
             nd.decode(dcode, x, 20, msg="bf16")

@@ -17,7 +17,8 @@ import paper_1202_1060_amd as nd  # noqa: E402
 from paper_1202_1060_amd.serve import Server, Requests  # noqa: E402
 from ldpcgen import workloads as W  # noqa: E402
 
-from parity import gpu_decode, syndrome_zero  # noqa: E402
+import oracle  # noqa: E402
+from parity import gpu_decode, syndrome_zero, compare  # noqa: E402
 
 DEV = torch.device("cuda:0")
 P = 160  # pool frames per code and Eb/N0 point
@@ -91,3 +92,27 @@ def test_admission_by_device_memory(setup):
     tiny = Server(s["codes"], policy="batched", budget_bytes=1000)
     with pytest.raises(ValueError):
         tiny.run(_stream(s, 10, None))
+
+
+def test_served_fp32_meets_the_oracle_bar(setup):
+    """Requests over the three resident codes served in mixed FP32 launches
+    (posteriors kept): every request's frames against the FP64 oracle."""
+    s = setup
+    srv = Server(s["codes"], policy="batched", msg="fp32", budget_bytes=64 << 20, max_inflight=3,
+                 posteriors=True)
+    N = 36
+    out = srv.run(_stream(s, N, None), keep_results=True)
+    assert out["launches"] < N
+    r = s["r"]
+    seen = set()
+    for i in range(N):
+        c, b, o, F = int(r["code"][i]), int(r["bin"][i]), int(s["off"][i]), int(r["frames"][i])
+        seen.add(c)
+        llr = s["pools"][c][0][b, o:o + F]
+        code = s["hcodes"][c]
+        n, rate = W.SERVE_CODES[c]
+        G, ov, wrap = W.serve_windows(n, rate)
+        ref = oracle.decode_with_sensitivity(code, oracle.windows(code.m, G, ov, bool(wrap)), llr, 20, True)
+        got = out["results"][i]
+        compare(dict(hard=got["hard"], post=got["post"], iters=got["iters"], syn_ok=got["syn_ok"]), ref)
+    assert seen == {0, 1, 2}
