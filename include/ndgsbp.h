@@ -166,6 +166,25 @@ int ldpc_decode(ldpc_code_t code, const float* llr, int32_t num_frames, int32_t 
                 uint32_t flags, uint8_t* hard, float* post, int32_t* iters, uint8_t* syn_ok,
                 void* hip_stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the same
+ * decode as ldpc_decode, same arguments, results and errors, bit for bit
+ * equal to it, but it allocates nothing. Its kernels take their work
+ * counter and, in the HBM tier, their workspace from one fixed device array
+ * of 64 MiB per GPU that the library holds from the first ldpc_code_create
+ * on that GPU until the process ends (bytes 0..255 the counters, the rest
+ * the workspace). HBM-tier decodes run as many 64-frame tiles at once as
+ * the array holds; a code one of whose tiles does not fit (e.g. n = 65000
+ * with four edges per VN and FP32 messages) is refused with
+ * LDPC_EUNSUPPORTED. Every call on a GPU shares that GPU's array and leaves
+ * its contents behind: calls on one stream are ordered, but calls that
+ * overlap on one GPU (other streams, other threads) race and give wrong
+ * results. Each call clears the counters with a small kernel on hip_stream
+ * before the decode, so it needs no memset and may be captured. */
+int ldpc_decode_noalloc(ldpc_code_t code, const float* llr, int32_t num_frames, int32_t max_iter,
+                        uint32_t flags, uint8_t* hard, float* post, int32_t* iters, uint8_t* syn_ok,
+                        void* hip_stream);
+
 /* ---- Batched decoding: many problems (codes, frame counts) per launch ----
  *
  * A batch decodes every frame of every problem with the schedule of

@@ -21,6 +21,7 @@ from ._native import (LdpcError, LDPC_OK, LDPC_EINVAL, LDPC_ENOMEM, LDPC_EHIP,
 
 __all__ = [
     "Code", "ldpc_code_create", "ldpc_code_destroy", "ldpc_code_query", "ldpc_code_tune", "ldpc_decode",
+    "ldpc_decode_noalloc",
     "ldpc_batch_create", "ldpc_batch_launch", "ldpc_batch_query", "ldpc_batch_destroy",
     "ldpc_decode_batched", "Problem", "Batch", "BatchOptions", "decode_batched", "new_outputs",
     "ldpc_last_error", "decode", "LdpcError", "msg_flag",
@@ -91,6 +92,17 @@ def ldpc_decode(handle, llr_ptr, num_frames, max_iter, flags, hard_ptr, post_ptr
                                    ctypes.c_void_p(hard_ptr), ctypes.c_void_p(post_ptr or None),
                                    ctypes.c_void_p(iters_ptr), ctypes.c_void_p(syn_ok_ptr or None),
                                    ctypes.c_void_p(stream or None)))
+
+
+def ldpc_decode_noalloc(handle, llr_ptr, num_frames, max_iter, flags, hard_ptr, post_ptr, iters_ptr,
+                        syn_ok_ptr, stream) -> None:
+    """ldpc_decode without allocation (fixed per-GPU scratch); same arguments."""
+    _native.check(_native.load().ldpc_decode_noalloc(ctypes.c_void_p(handle), ctypes.c_void_p(llr_ptr),
+                                                     int(num_frames), int(max_iter), int(flags),
+                                                     ctypes.c_void_p(hard_ptr), ctypes.c_void_p(post_ptr or None),
+                                                     ctypes.c_void_p(iters_ptr),
+                                                     ctypes.c_void_p(syn_ok_ptr or None),
+                                                     ctypes.c_void_p(stream or None)))
 
 
 def msg_flag(msg: str) -> int:

@@ -27,7 +27,7 @@ LDPC_FLAG_OUT_PACKED = 0x8
 LDPC_FLAG_TIER_HBM = 0x10
 
 EXPORTS = ("ldpc_code_create", "ldpc_code_destroy", "ldpc_code_query", "ldpc_code_tune",
-           "ldpc_decode", "ldpc_batch_create", "ldpc_batch_launch", "ldpc_batch_query",
+           "ldpc_decode", "ldpc_decode_noalloc", "ldpc_batch_create", "ldpc_batch_launch", "ldpc_batch_query",
            "ldpc_batch_destroy", "ldpc_decode_batched", "ldpc_last_error")
 
 _i32p = ctypes.POINTER(ctypes.c_int32)
@@ -102,6 +102,8 @@ def load() -> ctypes.CDLL:
     lib.ldpc_decode.restype = ctypes.c_int
     lib.ldpc_decode.argtypes = [vp, vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_uint32,
                                 vp, vp, vp, vp, vp]
+    lib.ldpc_decode_noalloc.restype = ctypes.c_int
+    lib.ldpc_decode_noalloc.argtypes = lib.ldpc_decode.argtypes
     lib.ldpc_batch_create.restype = ctypes.c_int
     lib.ldpc_batch_create.argtypes = [ctypes.POINTER(ldpc_problem), ctypes.c_int32, ctypes.c_uint32,
                                       ctypes.POINTER(ldpc_batch_options), ctypes.POINTER(vp)]

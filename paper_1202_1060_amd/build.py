@@ -12,7 +12,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 SOURCES = [os.path.join(HERE, "csrc", "ndgsbp_host.cpp"),
            os.path.join(HERE, "csrc", "ndgsbp_kernels.hip"),
-           os.path.join(HERE, "csrc", "ndgsbp_hbm.hip")]
+           os.path.join(HERE, "csrc", "ndgsbp_hbm.hip"),
+           os.path.join(HERE, "csrc", "ndgsbp_noalloc.hip")]
 OUT = os.path.join(HERE, "libndgsbp.so")
 OBJDIR = os.path.join(HERE, "_build")
 

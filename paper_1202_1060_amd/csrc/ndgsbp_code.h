@@ -63,3 +63,27 @@ struct ldpc_code {
     hipEvent_t hbm_last = nullptr;
     bool hbm_used = false;
 };
+
+namespace ndgsbp {
+
+// Device memory a caller supplies in place of the code's own work counters
+// and HBM-tier workspace: `work` two zeroed words, `hbm` a workspace of
+// `hbm_bytes` (the tiles in flight are bounded by it).
+struct Scratch {
+    uint32_t* work;
+    void* hbm;
+    size_t hbm_bytes;
+};
+
+// ldpc_decode with an optional Scratch (nullptr: the code's own buffers).
+int decode_enqueue(ldpc_code* c, const float* llr, int32_t num_frames, int32_t max_iter, uint32_t flags,
+                   uint8_t* hard, float* post, int32_t* iters, uint8_t* syn_ok, const Scratch* scratch,
+                   void* hip_stream);
+// Sets the thread's ldpc_last_error message; returns `code`.
+int record_error(int code, const char* msg);
+// Once per device, with that device current: locates the device's copy of
+// the fixed scratch array of ldpc_decode_noalloc and clears its counters
+// (ndgsbp_noalloc.hip).
+hipError_t noalloc_setup(int device);
+
+}  // namespace ndgsbp

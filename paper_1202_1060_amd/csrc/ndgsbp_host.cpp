@@ -713,9 +713,12 @@ hipError_t get_stage(int device, DeviceStage** out) {
 }
 
 // HBM tier (codes beyond LDS, or LDPC_FLAG_TIER_HBM): one-lane tables,
-// 64-frame tiles in a workspace the code keeps and grows on demand.
+// 64-frame tiles in a workspace. Without `scratch` the workspace is the
+// code's own, grown on demand, and the code's HBM-tier launches are ordered
+// on the device; with it, the caller's fixed buffer bounds the tiles in
+// flight and nothing is allocated or ordered.
 int decode_hbm(ldpc_code* c, const float* llr, int32_t num_frames, int32_t max_iter, uint32_t flags, uint8_t* hard,
-               float* post, int32_t* iters, uint8_t* syn_ok, hipStream_t stream) {
+               float* post, int32_t* iters, uint8_t* syn_ok, const Scratch* scratch, hipStream_t stream) {
     const MsgKind kind = msg_kind(flags);
     const Layout& lay = c->lay[0];
     if (!lay.valid) return fail(LDPC_EUNSUPPORTED, "no one-lane tables for the HBM tier");
@@ -730,13 +733,37 @@ int decode_hbm(ldpc_code* c, const float* llr, int32_t num_frames, int32_t max_i
     if (e != hipSuccess) return hip_fail(e, "occupancy query (HBM tier)");
     if (per_cu < 1) return fail(LDPC_EUNSUPPORTED, "HBM-tier kernel cannot be resident");
     const int64_t tiles_needed = (num_frames + slots - 1) / slots;
-    const int blocks = (int)std::min<int64_t>((int64_t)per_cu * c->num_cus, tiles_needed);
+    int blocks = (int)std::min<int64_t>((int64_t)per_cu * c->num_cus, tiles_needed);
     const uint64_t frows = (uint64_t)c->ds_start + (uint64_t)c->max_slots;
     const uint64_t fws_tile = frows * slots;
     const uint64_t mws_tile = (uint64_t)c->m * lay.D * slots;
     const size_t msg_size = kind == kMsgF32 ? 4 : 2;
     const size_t ftile_bytes = (fws_tile * 4 + 255) & ~(size_t)255;
-    const size_t need = (size_t)blocks * ftile_bytes + (size_t)blocks * mws_tile * msg_size;
+    const size_t tile_bytes = ftile_bytes + ((mws_tile * msg_size + 255) & ~(size_t)255);
+
+    HbmArgs a{};
+    a.p = make_problem(c, lay, llr, num_frames, max_iter, hard, post, iters, syn_ok);
+    a.vfirst = c->dev.vfirst;
+    a.fws_tile = ftile_bytes / 4;
+    a.mws_tile = mws_tile;
+    a.early_stop = (flags & LDPC_FLAG_EARLY_STOP) ? 1 : 0;
+    a.packed = (flags & LDPC_FLAG_OUT_PACKED) ? 1 : 0;
+    a.ymax = (float)(kXMax * kLog2e);
+    a.cmin = (float)kXMin;
+    if (scratch) {
+        const int64_t fit = (int64_t)(scratch->hbm_bytes / tile_bytes);
+        if (fit < 1)
+            return fail(LDPC_EUNSUPPORTED, "one HBM-tier tile of this code needs " + std::to_string(tile_bytes) +
+                                               " B, more than the " + std::to_string(scratch->hbm_bytes) +
+                                               " B of the fixed scratch buffer");
+        blocks = (int)std::min<int64_t>(blocks, fit);
+        a.fws = reinterpret_cast<float*>(scratch->hbm);
+        a.mws = reinterpret_cast<unsigned char*>(scratch->hbm) + (size_t)blocks * ftile_bytes;
+        a.work = scratch->work;
+        e = launch_hbm(a, kind, lay.D, lay.uniform, blocks, threads, stream);
+        return e == hipSuccess ? LDPC_OK : hip_fail(e, "HBM-tier decode launch");
+    }
+    const size_t need = (size_t)blocks * tile_bytes;
 
     std::lock_guard<std::mutex> lock(c->hbm_mu);
     if (!c->hbm_last) {
@@ -758,18 +785,9 @@ int decode_hbm(ldpc_code* c, const float* llr, int32_t num_frames, int32_t max_i
                                             : hip_fail(e, "HBM-tier workspace");
         c->hbm_ws_bytes = need;
     }
-    HbmArgs a{};
-    a.p = make_problem(c, lay, llr, num_frames, max_iter, hard, post, iters, syn_ok);
-    a.vfirst = c->dev.vfirst;
     a.fws = reinterpret_cast<float*>(c->hbm_ws);
     a.mws = reinterpret_cast<unsigned char*>(c->hbm_ws) + (size_t)blocks * ftile_bytes;
-    a.fws_tile = ftile_bytes / 4;
-    a.mws_tile = mws_tile;
     a.work = c->dev.work + 2 * (c->next_work.fetch_add(1) % kWorkRing);
-    a.early_stop = (flags & LDPC_FLAG_EARLY_STOP) ? 1 : 0;
-    a.packed = (flags & LDPC_FLAG_OUT_PACKED) ? 1 : 0;
-    a.ymax = (float)(kXMax * kLog2e);
-    a.cmin = (float)kXMin;
     if (c->hbm_used) {
         e = hipStreamWaitEvent(stream, c->hbm_last, 0);
         if (e != hipSuccess) return hip_fail(e, "HBM-tier ordering");
@@ -797,6 +815,59 @@ hipError_t reserve_slot(StageSlot& s, size_t n) {
 }
 
 }  // namespace
+
+namespace ndgsbp {
+
+int record_error(int code, const char* msg) { return fail(code, msg); }
+
+// ldpc_decode, with the work counter and HBM-tier workspace taken from
+// `scratch` when it is given (the code's own otherwise).
+int decode_enqueue(ldpc_code* c, const float* llr, int32_t num_frames, int32_t max_iter, uint32_t flags,
+                   uint8_t* hard, float* post, int32_t* iters, uint8_t* syn_ok, const Scratch* scratch,
+                   void* hip_stream) {
+    g_last_error.clear();
+    if (!c) return fail(LDPC_EINVAL, "code is NULL");
+    if (num_frames < 0) return fail(LDPC_EINVAL, "num_frames < 0");
+    if (max_iter < 1) return fail(LDPC_EINVAL, "max_iter < 1");
+    int rc = check_flags(flags);
+    if (rc) return rc;
+    if (num_frames == 0) return LDPC_OK;
+    if (!llr || !hard || !iters) return fail(LDPC_EINVAL, "llr, hard and iters are required");
+    const MsgKind kind = msg_kind(flags);
+    const Layout& lay = c->lay[c->lanes_for[kind] - 1];
+
+    DeviceGuard guard(c->device);
+    if (!guard.ok) return fail(LDPC_EHIP, "cannot select the code's device");
+    if (c->vertical) {
+        if ((flags & LDPC_FLAG_TIER_HBM) || lds_bytes(c, lay, kind) > c->max_lds)
+            return fail(LDPC_EUNSUPPORTED, "the vertical schedule runs in the LDS tier only");
+        if (kind == kMsgBF16 || lay.H > 2)
+            return fail(LDPC_EUNSUPPORTED, "the vertical schedule takes FP32 or FP16 messages, one or two lanes");
+    } else if ((flags & LDPC_FLAG_TIER_HBM) || lds_bytes(c, lay, kind) > c->max_lds) {
+        return decode_hbm(c, llr, num_frames, max_iter, flags, hard, post, iters, syn_ok, scratch,
+                          (hipStream_t)hip_stream);
+    }
+    LaunchShape shape;
+    shape.vertical = c->vertical;
+    shape.lanes = lay.H;
+    shape.threads = threads_for(c, lay);
+    shape.lds_bytes = lds_bytes(c, lay, kind);
+    rc = set_blocks(kind, lay.D, lay.uniform, false, c->num_cus, num_frames, shape);
+    if (rc) return rc;
+
+    DecodeArgs a{};
+    a.p0 = make_problem(c, lay, llr, num_frames, max_iter, hard, post, iters, syn_ok);
+    a.table = nullptr;
+    a.nprob = 1;
+    a.total_frames = num_frames;
+    a.work = scratch ? scratch->work : c->dev.work + 2 * (c->next_work.fetch_add(1) % kWorkRing);
+    set_launch_constants(a, flags, shape.lds_bytes);
+    hipError_t e = launch_decode(a, kind, lay.D, lay.uniform, shape, (hipStream_t)hip_stream);
+    if (e != hipSuccess) return hip_fail(e, "decode launch");
+    return LDPC_OK;
+}
+
+}  // namespace ndgsbp
 
 extern "C" {
 
@@ -1031,6 +1102,8 @@ int ldpc_code_create(const ldpc_h_csr* H, const ldpc_grouping* grouping, int32_t
         c->max_lds = (size_t)v;
     }
     if (e == hipSuccess) e = hipDeviceGetAttribute(&c->num_cus, hipDeviceAttributeMultiprocessorCount, device);
+    // set-up of ldpc_decode_noalloc's fixed scratch on this device (once)
+    if (e == hipSuccess) e = noalloc_setup(device);
     if (e == hipSuccess) {
         for (MsgKind k : {kMsgF32, kMsgF16, kMsgBF16}) {
             const int h = pick_lanes_resident(c, k, max_edges);
@@ -1099,45 +1172,8 @@ int ldpc_code_tune(ldpc_code_t c, uint32_t msg_flags, int32_t lanes_per_cn) {
 
 int ldpc_decode(ldpc_code_t c, const float* llr, int32_t num_frames, int32_t max_iter, uint32_t flags,
                 uint8_t* hard, float* post, int32_t* iters, uint8_t* syn_ok, void* hip_stream) {
-    g_last_error.clear();
-    if (!c) return fail(LDPC_EINVAL, "code is NULL");
-    if (num_frames < 0) return fail(LDPC_EINVAL, "num_frames < 0");
-    if (max_iter < 1) return fail(LDPC_EINVAL, "max_iter < 1");
-    int rc = check_flags(flags);
-    if (rc) return rc;
-    if (num_frames == 0) return LDPC_OK;
-    if (!llr || !hard || !iters) return fail(LDPC_EINVAL, "llr, hard and iters are required");
-    const MsgKind kind = msg_kind(flags);
-    const Layout& lay = c->lay[c->lanes_for[kind] - 1];
-
-    DeviceGuard guard(c->device);
-    if (!guard.ok) return fail(LDPC_EHIP, "cannot select the code's device");
-    if (c->vertical) {
-        if ((flags & LDPC_FLAG_TIER_HBM) || lds_bytes(c, lay, kind) > c->max_lds)
-            return fail(LDPC_EUNSUPPORTED, "the vertical schedule runs in the LDS tier only");
-        if (kind == kMsgBF16 || lay.H > 2)
-            return fail(LDPC_EUNSUPPORTED, "the vertical schedule takes FP32 or FP16 messages, one or two lanes");
-    } else if ((flags & LDPC_FLAG_TIER_HBM) || lds_bytes(c, lay, kind) > c->max_lds) {
-        return decode_hbm(c, llr, num_frames, max_iter, flags, hard, post, iters, syn_ok, (hipStream_t)hip_stream);
-    }
-    LaunchShape shape;
-    shape.vertical = c->vertical;
-    shape.lanes = lay.H;
-    shape.threads = threads_for(c, lay);
-    shape.lds_bytes = lds_bytes(c, lay, kind);
-    rc = set_blocks(kind, lay.D, lay.uniform, false, c->num_cus, num_frames, shape);
-    if (rc) return rc;
-
-    DecodeArgs a{};
-    a.p0 = make_problem(c, lay, llr, num_frames, max_iter, hard, post, iters, syn_ok);
-    a.table = nullptr;
-    a.nprob = 1;
-    a.total_frames = num_frames;
-    a.work = c->dev.work + 2 * (c->next_work.fetch_add(1) % kWorkRing);
-    set_launch_constants(a, flags, shape.lds_bytes);
-    hipError_t e = launch_decode(a, kind, lay.D, lay.uniform, shape, (hipStream_t)hip_stream);
-    if (e != hipSuccess) return hip_fail(e, "decode launch");
-    return LDPC_OK;
+    return ndgsbp::decode_enqueue(c, llr, num_frames, max_iter, flags, hard, post, iters, syn_ok, nullptr,
+                                  hip_stream);
 }
 
 int ldpc_batch_create(const ldpc_problem* probs, int32_t count, uint32_t flags, const ldpc_batch_options* opt,

@@ -19,7 +19,7 @@ def _declared():
 
 def test_header_declares_the_abi():
     assert _declared() == sorted(["ldpc_code_create", "ldpc_code_destroy", "ldpc_code_query",
-                                  "ldpc_code_tune", "ldpc_decode", "ldpc_batch_create",
+                                  "ldpc_code_tune", "ldpc_decode", "ldpc_decode_noalloc", "ldpc_batch_create",
                                   "ldpc_batch_launch", "ldpc_batch_query", "ldpc_batch_destroy",
                                   "ldpc_decode_batched", "ldpc_last_error"])
 
