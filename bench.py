@@ -10,12 +10,15 @@ and syndrome flags written back to HBM).
 
 Prints one JSON line. The decoded info rate counts K = 1152 information bits
 per frame. The roofline object is for the decode kernel, bound by VALU issue
-(26 issue slots per edge update, derived below). Further legs in the same
-line: fixed iterations, FP16 messages, the same frames under the baseline
-schedules (flooding BP, disjoint GSBP, vertical GSBP), the 256-problem mixed
-batch against one FP32 launch per problem, the HBM tier, and request serving
-with continuous batching (p50/p99 latency) against one FP32 launch per
-request.
+(34 full-rate slots per edge update against the chip's FP32 vector peak,
+derived below; beside it the fraction of the bound that the measured issue
+rates of plain FP32 code give). Further legs in the same line: fixed
+iterations, FP16 messages, the same frames under the baseline schedules
+(flooding BP, disjoint GSBP, vertical GSBP), the 256-problem mixed batch
+(FP16 and FP32 messages) against one FP32 launch per problem, the HBM tier,
+and request serving with continuous batching (p50/p99 latency, LLRs resident
+in device memory or staged from pinned host memory) against one FP32 launch
+per request.
 """
 from __future__ import annotations
 
@@ -32,14 +35,26 @@ sys.path.insert(0, ROOT)
 
 METRIC = "decoded info Gbit/s at matched FER (served/batched vs plain); p50/p99 latency"
 
-# VALU issue slots per edge update that the method itself needs: two phi
-# evaluations of 1 exp + 1 log + 1 reciprocal (transcendentals issue at half
-# the full FP32 rate on gfx950, 2 slots each) plus three full-rate ops each,
-# and eight full-rate ops for the extrinsic, clamps, exclusive sum, signs and
-# add-back: 2 * (6 + 3) + 8 = 26.
-SLOTS_PER_EDGE_UPDATE = 26
-# 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz, one non-packed VALU op per lane-cycle
-PEAK_SLOTS_PER_S = 256 * 4 * 16 * 2.4e9
+# VALU work per edge update that the method itself needs, in full-rate FP32
+# issue slots: two phi evaluations of one exp, one log and one reciprocal
+# each (6 transcendentals, a quarter of the FP32 rate, 4 slots each) and
+# about ten full-rate ops (extrinsic, clamp, exclusive sums, sign, add-back):
+# 6 * 4 + 10 = 34.
+SLOTS_PER_EDGE_UPDATE = 34
+TRANSCENDENTALS_PER_EDGE_UPDATE = 6
+FULL_RATE_PER_EDGE_UPDATE = 10
+# Peak from the chip's figures: FP32 vector 157.3 TFLOP/s = 256 CUs x 2.4 GHz
+# x 128 FMA lane-slots per CU-cycle = 78.6 T slots/s (an FMA is one slot)
+PEAK_SLOTS_PER_S = 256 * 128 * 2.4e9
+# Issue rates measured on MI355X by the probes of --calibrate-valu (the
+# fastest of repeated runs; FMA with 16 independent chains per lane,
+# exp2 + log2 with 8): a second bound from what plain FP32 code attains,
+# transcendentals and full-rate ops sharing the issue slots (the mixed
+# probe takes 1.02 x the sum of its parts)
+MEASURED_FMA_PER_S = 55.90e12
+MEASURED_TRANS_PER_S = 17.82e12
+EDGE_UPDATES_PER_S_MEASURED_BOUND = 1.0 / (TRANSCENDENTALS_PER_EDGE_UPDATE / MEASURED_TRANS_PER_S
+                                           + FULL_RATE_PER_EDGE_UPDATE / MEASURED_FMA_PER_S)
 
 
 def log(*a):
@@ -83,10 +98,25 @@ def make_inputs(rec, frames_per_snr):
     return np.concatenate(llrs), np.concatenate(cws)
 
 
-def cpu_baseline(code, groups, llr, rec, frames_per_snr, seconds, k_info):
+def physical_cores():
+    """Physical cores of the host (distinct core/socket pairs of lscpu), or None."""
+    import subprocess
+    try:
+        out = subprocess.run(["lscpu", "-p=core,socket"], capture_output=True, text=True, timeout=10).stdout
+    except (OSError, subprocess.SubprocessError):
+        return None
+    pairs = {line.strip() for line in out.splitlines() if line and not line.startswith("#")}
+    return len(pairs) or None
+
+
+def cpu_baseline(code, groups, llr, rec, frames_per_snr, seconds, k_info, gpu_hard=None):
     """The FP64 oracle on the host cores over a bounded sample of the same
     workload: the first F frames of every Eb/N0 point, F sized by a pilot run
-    of 16 frames per point so that the timed run takes about ``seconds``."""
+    of 16 frames per point so that the timed run takes about ``seconds``;
+    then a one-thread run over a quarter of that sample, and the one-ulp
+    sensitivity control (the same frames with every LLR moved by one float32
+    ulp) whose decision changes are reported per Eb/N0 beside the GPU's
+    decision mismatches on the same frames."""
     import oracle
     points = len(rec["ebn0"])
 
@@ -101,11 +131,33 @@ def cpu_baseline(code, groups, llr, rec, frames_per_snr, seconds, k_info):
     t0 = time.perf_counter()
     out = oracle.decode(code, groups, llr[idx], rec["max_iter"], rec["early_stop"], nthreads=0)
     dt = time.perf_counter() - t0
+    # one thread, a quarter of the sample
+    per1 = max(1, per_snr // 4)
+    idx1 = sample(per1)
+    t0 = time.perf_counter()
+    one = oracle.decode(code, groups, llr[idx1], rec["max_iter"], rec["early_stop"], nthreads=1)
+    dt1 = time.perf_counter() - t0
+    # sensitivity control on the all-thread sample
+    ctl = oracle.decode(code, groups, oracle.perturb_one_ulp(llr[idx]), rec["max_iter"], rec["early_stop"],
+                        nthreads=0)
+    rows = []
+    for i, eb in enumerate(rec["ebn0"]):
+        sl = slice(i * per_snr, (i + 1) * per_snr)
+        ref_h = out["hard"][sl]
+        row = {"ebn0": eb, "frames": per_snr, "oracle_decoded": int(out["syn_ok"][sl].sum()),
+               "control_decision_changes": int(np.any(ctl["hard"][sl] != ref_h, axis=1).sum())}
+        if gpu_hard is not None:
+            row["gpu_decision_mismatches"] = int(np.any(gpu_hard[idx[sl]] != ref_h, axis=1).sum())
+        rows.append(row)
     return dict(value=len(idx) * k_info / dt / 1e9, unit="Gbit/s", cores=int(out["threads"]),
                 kind="oracle",
                 sample=f"first {per_snr} frames of each of the {points} Eb/N0 "
                        f"points ({len(idx)} frames), FP64, {dt:.1f} s",
-                seconds=dt)
+                seconds=dt, logical_cpus=os.cpu_count(), physical_cores=physical_cores(),
+                one_thread={"value": len(idx1) * k_info / dt1 / 1e9, "unit": "Gbit/s", "cores": int(one["threads"]),
+                            "sample": f"first {per1} frames of each Eb/N0 point ({len(idx1)} frames), {dt1:.1f} s",
+                            "frames_per_s": len(idx1) / dt1},
+                frames_per_s=len(idx) / dt, sensitivity_control=rows)
 
 
 def clopper_pearson(k, n, alpha=0.05):
@@ -191,6 +243,16 @@ def bench_batched(args, torch, nd, W, dev, log):
     del graph
     batch.close()
 
+    # the same batch with FP32 messages (precision separated from batching)
+    probs32 = [nd.Problem(c, x, p["max_iter"], want_post=False) for c, x, p in zip(codes, llrs, specs)]
+    opts32 = autotune.tune_batch(probs32, msg="fp32", early_stop=rec["early_stop"], cache=args.tune_cache)
+    batch32 = nd.Batch(probs32, msg="fp32", early_stop=rec["early_stop"], options=opts32)
+    b32wall, b32ms = timed(lambda: batch32.launch(stream), args.batch_steps)
+    b32stats = fer([p.out for p in probs32])
+    b32info = batch32.info
+    batch32.close()
+    log(f"batched fp32 options {opts32}: {bits / (b32ms * 1e-3) / 1e9:.2f} Gbit/s")
+
     plain_out = [nd.new_outputs(p["frames"], c.n, dev, want_post=False) for p, c in zip(specs, codes)]
 
     def plain():
@@ -216,6 +278,11 @@ def bench_batched(args, torch, nd, W, dev, log):
                          **bstats},
         "batched_fp16_graph_replay": {"gbit_s": bits / (gms * 1e-3) / 1e9, "ms": gms, "wall_ms": gwall * 1e3,
                                       "frame_errors": gstats["frame_errors"]},
+        "batched_fp32": {"gbit_s": bits / (b32ms * 1e-3) / 1e9, "ms": b32ms, "wall_ms": b32wall * 1e3,
+                         "edge_updates_per_s": b32stats["edge_updates"] / (b32ms * 1e-3),
+                         "roofline_frac": b32stats["edge_updates"] * SLOTS_PER_EDGE_UPDATE / (b32ms * 1e-3)
+                         / PEAK_SLOTS_PER_S,
+                         "launches": b32info["num_launches"], "options": list(opts32.as_tuple()), **b32stats},
         "plain_fp32_per_problem": {"gbit_s": bits / (pms * 1e-3) / 1e9, "ms": pms, "wall_ms": pwall * 1e3,
                                    "edge_updates_per_s": pstats["edge_updates"] / (pms * 1e-3),
                                    "launches": len(specs), **pstats},
@@ -288,85 +355,193 @@ def bench_hbm(args, torch, nd, W, dev, log, sweep_llr, sweep_k):
     return out
 
 
+def serving_frames(torch, W, dev, r, pool, codes):
+    """LLRs of every request of the serving stream at its own Eb/N0 (drawn
+    continuously from U[1.5, 3.5] dB): request i takes pool rows
+    off_i .. off_i + F_i - 1 of its code's channel pool (codewords and unit
+    noise, ldpcgen.workloads.serve_symbols) at sigma_i, L = (2/sigma^2)
+    (x + sigma w). Built on the device into one float32 buffer holding the
+    requests back to back in arrival order. Returns (buffer, element offsets,
+    pool row offsets, codeword pools)."""
+    from ldpcgen.channel import ebn0_to_sigma
+    N = len(r["frames"])
+    nvec = np.array([c.n for c in codes], dtype=np.int64)
+    F = r["frames"]
+    off = np.minimum((r["u"] * (pool - F + 1)).astype(np.int64), pool - F)
+    elems = F * nvec[r["code"]]
+    host_off = np.concatenate([[0], np.cumsum(elems)])
+    buf = torch.empty(int(host_off[-1]), dtype=torch.float32, device=dev)
+    cws = []
+    for ci, (n, rate) in enumerate(W.SERVE_CODES):
+        cw, w = W.serve_symbols(ci, pool)
+        cws.append(cw)
+        x = torch.from_numpy(1.0 - 2.0 * cw.astype(np.float32)).to(dev)
+        wn = torch.from_numpy(w).to(dev)
+        idx = np.nonzero(r["code"] == ci)[0]
+        if len(idx) == 0:
+            continue
+        enc_rate = W.encoder_for(W.qc_key(n, rate)).rate
+        sig = np.array([ebn0_to_sigma(float(e), enc_rate) for e in r["ebn0"][idx]], dtype=np.float64)
+        # one entry per frame: pool row, scales and destination offset
+        fr = F[idx]
+        rows = np.concatenate([np.arange(o, o + f) for o, f in zip(off[idx], fr)])
+        a = np.repeat(2.0 / sig ** 2, fr).astype(np.float32)
+        bsc = np.repeat(2.0 / sig, fr).astype(np.float32)
+        dst = np.concatenate([h + n * np.arange(f) for h, f in zip(host_off[idx], fr)])
+        ar = torch.arange(n, device=dev)
+        for c0 in range(0, len(rows), 4096):
+            sl = slice(c0, c0 + 4096)
+            rt = torch.from_numpy(rows[sl]).to(dev)
+            vals = torch.from_numpy(a[sl]).to(dev)[:, None] * x[rt] + torch.from_numpy(bsc[sl]).to(dev)[:, None] * wn[rt]
+            d = (torch.from_numpy(dst[sl]).to(dev)[:, None] + ar[None, :]).reshape(-1)
+            buf.index_copy_(0, d, vals.reshape(-1))
+        del x, wn
+    torch.cuda.synchronize()
+    return buf, host_off, off, cws
+
+
 def bench_serving(args, torch, nd, W, dev, log):
-    """Serving over the three resident QC codes: saturated throughput of the
-    continuous-batching server, then Poisson arrivals at 0.5x and 0.8x of it
-    for the batched FP16 server and the per-request FP32 policy."""
+    """Serving over the three resident QC codes, requests at continuous
+    Eb/N0. Two legs on the same request stream: LLRs already in device
+    memory, and LLRs arriving in pinned host memory as FP16 (staged to the
+    device by one copy per launch, inside each request's latency). Per leg:
+    saturated throughput of the continuous-batching server and of the
+    per-request FP32 policy; Poisson arrivals at 0.5x and 0.8x of each
+    policy's own saturated rate (p50/p99), and the per-request policy at the
+    batched server's offered load; frame error rates of both policies."""
     from paper_1202_1060_amd.serve import Server, Requests
     P = args.serve_pool
+    N = args.serve_requests
     t0 = time.perf_counter()
-    codes, pools, cws, ks = [], [], [], []
+    codes, ks = [], []
     for ci, (n, rate) in enumerate(W.SERVE_CODES):
         key = W.qc_key(n, rate)
-        llr, cw = W.serve_pool(ci, P)
-        pools.append(torch.from_numpy(llr).to(dev))
-        cws.append(cw)
         ks.append(W.encoder_for(key).k)
         codes.append(nd.Code(W.CODES[key](), windows=W.serve_windows(n, rate)))
-    log(f"serving pools: {P} frames x {len(W.SERVE_BINS)} Eb/N0 points x 3 codes in "
-        f"{time.perf_counter() - t0:.1f} s")
-    N = args.serve_requests
     r = W.serve_requests(count=N)
-    nvec = np.array([c.n for c in codes], dtype=np.int64)
+    buf, host_off, off, cws = serving_frames(torch, W, dev, r, P, codes)
+    host = torch.empty(buf.numel(), dtype=torch.float16, pin_memory=True)
+    for c0 in range(0, buf.numel(), 1 << 28):
+        host[c0:c0 + (1 << 28)].copy_(buf[c0:c0 + (1 << 28)].half())
+    torch.cuda.synchronize()
+    log(f"serving frames: {int(r['frames'].sum())} frames of {N} requests, {buf.numel() * 4 / 1e9:.2f} GB FP32 "
+        f"on the device, {host.numel() * 2 / 1e9:.2f} GB FP16 pinned on the host, in {time.perf_counter() - t0:.1f} s")
     kvec = np.array(ks, dtype=np.int64)
-    off = np.minimum((r["u"] * (P - r["frames"] + 1)).astype(np.int64), P - r["frames"])
-    base = np.array([p.data_ptr() for p in pools], dtype=np.uint64)
-    addr = base[r["code"]] + ((r["bin"] * P + off) * nvec[r["code"]] * 4).astype(np.uint64)
     bits = r["frames"] * kvec[r["code"]]
     max_iter = np.full(N, W.SERVE["max_iter"], dtype=np.int32)
+    addr = np.uint64(buf.data_ptr()) + (4 * host_off[:-1]).astype(np.uint64)
 
-    def stream_at(rate, count):
+    def stream_at(rate, count, staged):
         arr = np.zeros(count) if rate is None else r["arrival"][:count] / rate
+        if staged:
+            return Requests(arr, r["code"][:count], r["frames"][:count], None, max_iter[:count],
+                            host_llr=host, host_off=host_off[:count + 1])
         return Requests(arr, r["code"][:count], r["frames"][:count], addr[:count], max_iter[:count])
 
     def fer(res, count):
         err = 0
         for i in range(count):
-            c, b, o, F = int(r["code"][i]), int(r["bin"][i]), int(off[i]), int(r["frames"][i])
-            err += int(np.any(res[i]["hard"] != cws[c][b, o:o + F], axis=1).sum())
+            c, o, F = int(r["code"][i]), int(off[i]), int(r["frames"][i])
+            err += int(np.any(res[i]["hard"] != cws[c][o:o + F], axis=1).sum())
         tot = int(r["frames"][:count].sum())
         lo, hi = clopper_pearson(err, tot)
         return dict(fer=err / tot, frame_errors=err, frames=tot, ci95=[lo, hi])
 
+    def summary(o, count):
+        return {"requests": count, "p50_ms": o["p50_ms"], "p99_ms": o["p99_ms"],
+                "gbit_s": float(bits[:count].sum()) / o["makespan"] / 1e9, "launches": o["launches"]}
+
+    out = {"workload": "3 resident QC codes (n=648 R=5/6, n=1944 R=1/2, n=8064 R=1/2, z=n/24, one base row "
+                       "per window, overlap floor(z/4)); Poisson arrivals; requests of 1-512 frames "
+                       "(geometric, mean 32), Eb/N0 U[1.5,3.5] dB drawn per request, I_max 20, syndrome stop",
+           "requests": N, "frames": int(r["frames"].sum())}
     batched = Server(codes, policy="batched", msg="fp16", budget_bytes=args.serve_budget,
                      max_inflight=args.serve_inflight)
     plain = Server(codes, policy="plain", budget_bytes=args.serve_budget)
-    # warm-up (allocator, kernels), then saturation: everything arrives at 0
-    batched.run(stream_at(None, min(N, 2000)))
-    plain.run(stream_at(None, 200))
-    sat = batched.run(stream_at(None, N))
-    sat_rate = N / sat["makespan"]
-    out = {"workload": "3 resident QC codes (n=648 R=5/6, n=1944 R=1/2, n=8064 R=1/2, z=n/24, one base row "
-                       "per window, overlap floor(z/4)); requests of 1-512 frames (geometric, mean 32), "
-                       "Eb/N0 U[1.5,3.5] dB, I_max 20, syndrome stop; request LLRs device-resident",
-           "requests": N, "frames": int(r["frames"].sum()),
-           "saturated": {"req_s": sat_rate, "gbit_s": float(bits.sum()) / sat["makespan"] / 1e9,
-                         "launches": sat["launches"], "p50_ms": sat["p50_ms"], "p99_ms": sat["p99_ms"]},
-           "loads": []}
-    log(f"serving saturated: {sat_rate:.0f} req/s, {out['saturated']['gbit_s']:.2f} Gbit/s")
-    for load in (0.5, 0.8):
-        rate = load * sat_rate
-        b = batched.run(stream_at(rate, N))
+    for staged in (False, True):
+        leg = {"llr_source": "pinned host memory, FP16, one copy per launch inside the latency" if staged
+               else "device memory (resident before arrival)"}
+        # warm-up, then saturation: everything arrives at 0
+        batched.run(stream_at(None, min(N, 2000), staged))
+        plain.run(stream_at(None, 200, staged))
+        sat = batched.run(stream_at(None, N, staged))
+        sat_rate = N / sat["makespan"]
         npl = min(N, args.serve_plain_requests)
-        p = plain.run(stream_at(rate, npl))
-        row = {"load": load, "offered_req_s": rate,
-               "batched_fp16": {"requests": N, "p50_ms": b["p50_ms"], "p99_ms": b["p99_ms"],
-                                "gbit_s": float(bits.sum()) / b["makespan"] / 1e9, "launches": b["launches"]},
-               "plain_fp32": {"requests": npl, "p50_ms": p["p50_ms"], "p99_ms": p["p99_ms"],
-                              "gbit_s": float(bits[:npl].sum()) / p["makespan"] / 1e9,
-                              "launches": p["launches"]}}
-        log(f"serving load {load}: batched p50 {b['p50_ms']:.2f} p99 {b['p99_ms']:.2f} ms; "
-            f"plain p50 {p['p50_ms']:.2f} p99 {p['p99_ms']:.2f} ms")
-        out["loads"].append(row)
-    # matched FER: outputs of both policies on the same requests (untimed)
-    nv = min(N, args.serve_verify)
-    vb = batched.run(stream_at(None, nv), keep_results=True)
-    vp = plain.run(stream_at(None, nv), keep_results=True)
-    out["fer_batched_fp16"] = fer(vb["results"], nv)
-    out["fer_plain_fp32"] = fer(vp["results"], nv)
+        psat = plain.run(stream_at(None, npl, staged))
+        psat_rate = npl / psat["makespan"]
+        leg["saturated"] = {"batched_fp16": {"req_s": sat_rate, **summary(sat, N)},
+                            "plain_fp32": {"req_s": psat_rate, **summary(psat, npl)}}
+        log(f"serving ({'staged' if staged else 'resident'}) saturated: batched {sat_rate:.0f} req/s "
+            f"{leg['saturated']['batched_fp16']['gbit_s']:.2f} Gbit/s; plain {psat_rate:.0f} req/s "
+            f"{leg['saturated']['plain_fp32']['gbit_s']:.2f} Gbit/s")
+        leg["loads"] = []
+        for load in (0.5, 0.8):
+            b = batched.run(stream_at(load * sat_rate, N, staged))
+            p = plain.run(stream_at(load * psat_rate, npl, staged))
+            row = {"load": load, "batched_fp16": {"offered_req_s": load * sat_rate, **summary(b, N)},
+                   "plain_fp32": {"offered_req_s": load * psat_rate, **summary(p, npl)}}
+            log(f"serving ({'staged' if staged else 'resident'}) load {load}: batched p50 {b['p50_ms']:.2f} "
+                f"p99 {b['p99_ms']:.2f} ms; plain (own load) p50 {p['p50_ms']:.2f} p99 {p['p99_ms']:.2f} ms")
+            leg["loads"].append(row)
+        # the per-request policy at the batched server's half load
+        nq = min(N, args.serve_plain_requests // 2)
+        q = plain.run(stream_at(0.5 * sat_rate, nq, staged))
+        leg["plain_fp32_at_batched_half_load"] = {"offered_req_s": 0.5 * sat_rate, **summary(q, nq)}
+        # matched FER: outputs of both policies on the same requests (untimed)
+        nv = min(N, args.serve_verify)
+        vb = batched.run(stream_at(None, nv, staged), keep_results=True)
+        vp = plain.run(stream_at(None, nv, staged), keep_results=True)
+        leg["fer_batched_fp16"] = fer(vb["results"], nv)
+        leg["fer_plain_fp32"] = fer(vp["results"], nv)
+        out["staged_fp16_host" if staged else "device_resident"] = leg
+    del host, buf
     for c in codes:
         c.close()
     return out
+
+
+def calibrate_valu(torch, dev):
+    """Lane-operations per second of the VALU probes (libndgsbp_probe.so):
+    FMA with 8 and 16 independent chains per lane, add (16), exp2+log2 and
+    reciprocal (8), and a mix of 16 FMA and 4 exp2+log2 chains; the best of
+    three launches of 2048 x 256 threads each, per CU-cycle at the 2.4 GHz
+    peak clock. For the mix: its time per loop trip against the FMA-only and
+    transcendental-only times of the same work (additive if the two kinds
+    share the issue slots)."""
+    import ctypes
+    from paper_1202_1060_amd import build
+    lib = ctypes.CDLL(build.PROBE_OUT)
+    lib.ndgsbp_probe_valu.restype = ctypes.c_int
+    lib.ndgsbp_probe_valu.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_void_p,
+                                      ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_double)]
+    blocks = 2048
+    out = torch.empty(blocks * 256, dtype=torch.float32, device=dev)
+    torch.cuda.synchronize()
+    res = {}
+    kinds = ((0, "fma_8", 100000), (3, "fma_16", 50000), (4, "add_16", 50000), (1, "exp2_log2_8", 50000),
+             (2, "rcp_8", 100000), (5, "mix_fma16_trans8", 40000))
+    for kind, name, iters in kinds:
+        best = None
+        for _ in range(3):
+            ms, ops = ctypes.c_float(), ctypes.c_double()
+            rc = lib.ndgsbp_probe_valu(kind, blocks, iters, ctypes.c_void_p(out.data_ptr()),
+                                       ctypes.byref(ms), ctypes.byref(ops))
+            if rc != 0:
+                raise RuntimeError(f"probe {name} failed: hip error {rc}")
+            if best is None or ms.value < best[0]:
+                best = (ms.value, ops.value)
+        ms, ops = best
+        res[name] = {"ms": ms, "lane_ops": ops, "lane_ops_per_s": ops / (ms * 1e-3),
+                     "per_cu_cycle_at_2_4ghz": ops / (ms * 1e-3) / (256 * 2.4e9)}
+    # seconds per lane-op of each kind, and the mix against the sum of its parts
+    t_fma = 1.0 / res["fma_16"]["lane_ops_per_s"]
+    t_trans = 1.0 / res["exp2_log2_8"]["lane_ops_per_s"]
+    mix_ops = res["mix_fma16_trans8"]["lane_ops"]
+    fma_part, trans_part = mix_ops * 16 / 24, mix_ops * 8 / 24
+    additive = fma_part * t_fma + trans_part * t_trans
+    res["mix_vs_additive"] = res["mix_fma16_trans8"]["ms"] * 1e-3 / additive
+    res["trans_vs_fma"] = res["exp2_log2_8"]["lane_ops_per_s"] / res["fma_16"]["lane_ops_per_s"]
+    return {"calibrate_valu": res, "threads": blocks * 256}
 
 
 def main():
@@ -376,7 +551,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--msg", default="fp32", choices=["fp32", "fp16", "bf16"])
     ap.add_argument("--frames-per-snr", type=int, default=16384)
-    ap.add_argument("--cpu-seconds", type=float, default=12.0,
+    ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="target duration of the CPU-baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fixed", action="store_true", help="skip the fixed-iteration pass")
@@ -394,11 +569,13 @@ def main():
     ap.add_argument("--hbm-steps", type=int, default=3)
     ap.add_argument("--hbm-big-frames", type=int, default=32768)
     ap.add_argument("--serve-requests", type=int, default=30000)
-    ap.add_argument("--serve-plain-requests", type=int, default=6000)
+    ap.add_argument("--serve-plain-requests", type=int, default=3000)
     ap.add_argument("--serve-verify", type=int, default=2000)
     ap.add_argument("--serve-pool", type=int, default=1024)
     ap.add_argument("--serve-budget", type=int, default=2 << 30)
     ap.add_argument("--serve-inflight", type=int, default=4)
+    ap.add_argument("--calibrate-valu", action="store_true",
+                    help="only run the VALU issue-rate probes (FMA, exp2+log2, reciprocal)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device copy (for scaling HBM byte counters)")
     args = ap.parse_args()
@@ -413,6 +590,9 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
+    if args.calibrate_valu:
+        print(json.dumps(calibrate_valu(torch, dev)), flush=True)
+        return
     if args.calibrate_copy:
         # one device-to-device copy of 1 GiB: the counters of this dispatch read
         # 1 GiB fetched and 1 GiB written
@@ -494,7 +674,10 @@ def main():
         "fer": fer_table(iters, hard),
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_SLOTS_PER_S / 1e12,
                      "unit": "T VALU-slots/s", "frac": achieved / PEAK_SLOTS_PER_S,
-                     "traffic": measured_traffic(args.msg)},
+                     "traffic": measured_traffic(args.msg),
+                     "slots_per_edge_update": SLOTS_PER_EDGE_UPDATE,
+                     "frac_of_measured_issue_rates": edge_updates / (kern_ms * 1e-3)
+                     / EDGE_UPDATES_PER_S_MEASURED_BOUND},
     }
     if not args.no_fixed:
         fwall, fk, _, _ = measure(max(1, args.steps // 2), False, args.msg)
@@ -557,7 +740,7 @@ def main():
         import oracle
         groups = oracle.windows(code.m, *rec["windows"][:2], bool(rec["windows"][2]))
         result["cpu_baseline"] = cpu_baseline(code, groups, llr_np, rec, args.frames_per_snr,
-                                              args.cpu_seconds, enc.k)
+                                              args.cpu_seconds, enc.k, gpu_hard=hard)
     dcode.close()
     print(json.dumps(result), flush=True)
 

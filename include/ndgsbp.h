@@ -260,8 +260,11 @@ int ldpc_batch_destroy(ldpc_batch_t batch);
  * ldpc_decode: the problem table is staged through a per-device ring of 16
  * pinned-host/device slots that the library keeps for the life of the
  * process, so a call allocates nothing once its slot is large enough (the
- * 17th call in flight waits on the host for the 1st to finish). At most 64
- * launch classes per call. Not for graph capture (use ldpc_batch_launch).
+ * 17th call in flight waits on the host for the 1st to finish). Each slot
+ * has its own streams for the launch classes it forks from hip_stream, so
+ * calls in flight at once on different caller streams do not wait behind
+ * each other's classes. At most 64 launch classes per call. Not for graph
+ * capture (use ldpc_batch_launch).
  * Errors: as ldpc_batch_create, plus EUNSUPPORTED for too many classes. */
 int ldpc_decode_batched(const ldpc_problem* probs, int32_t count, uint32_t flags, void* hip_stream);
 

@@ -171,6 +171,21 @@ def serve_pool(code_index: int, frames_per_bin: int, recipe: dict = SERVE):
     return llr, cw
 
 
+def serve_symbols(code_index: int, pool: int, recipe: dict = SERVE):
+    """Channel pool of one serving code for requests at any Eb/N0: ``pool``
+    codewords of random information bits (uint8 (pool, n)) and unit-variance
+    Gaussian noise (float32 (pool, n)), seeded per code. A frame drawn from
+    pool row j at noise level sigma has LLRs (2 / sigma^2) (x + sigma w) with
+    x = 1 - 2 c (BPSK)."""
+    n, rate = SERVE_CODES[code_index]
+    enc = encoder_for(qc_key(n, rate))
+    rng = _philox(recipe["seed"], 1, code_index)
+    u = rng.integers(0, 2, size=(pool, enc.k), dtype=np.uint8)
+    cw = enc.encode(u)
+    w = rng.standard_normal((pool, n), dtype=np.float32)
+    return cw, w
+
+
 def problem_frames(prob: dict, num_frames: int | None = None):
     """LLRs and codewords of a batched problem or a serving request."""
     enc = encoder_for(prob["code"])

@@ -15,6 +15,9 @@ SOURCES = [os.path.join(HERE, "csrc", "ndgsbp_host.cpp"),
            os.path.join(HERE, "csrc", "ndgsbp_hbm.hip"),
            os.path.join(HERE, "csrc", "ndgsbp_noalloc.hip")]
 OUT = os.path.join(HERE, "libndgsbp.so")
+# issue-rate probes of the VALU (the bench's roofline calibration), a library of their own
+PROBE_SRC = os.path.join(HERE, "csrc", "ndgsbp_probe.hip")
+PROBE_OUT = os.path.join(HERE, "libndgsbp_probe.so")
 OBJDIR = os.path.join(HERE, "_build")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
@@ -36,6 +39,7 @@ def build(verbose: bool = False) -> str:
     os.makedirs(OBJDIR, exist_ok=True)
     objs = [os.path.join(OBJDIR, os.path.basename(src) + ".o") for src in SOURCES]
     cmds = [[HIPCC, *FLAGS, "-c", src, "-o", obj] for src, obj in zip(SOURCES, objs)]
+    cmds.append([HIPCC, *FLAGS, "-shared", PROBE_SRC, "-o", PROBE_OUT + ".tmp"])
     with ThreadPoolExecutor(max_workers=len(cmds)) as ex:
         results = list(ex.map(_run, cmds))
     for res in results:
@@ -44,6 +48,7 @@ def build(verbose: bool = False) -> str:
             raise RuntimeError("hipcc failed")
         if verbose:
             sys.stderr.write(res.stderr)
+    os.replace(PROBE_OUT + ".tmp", PROBE_OUT)
     tmp = OUT + ".tmp"
     res = _run([HIPCC, "--offload-arch=gfx950", "-shared", *objs, "-o", tmp])
     if res.returncode != 0:

@@ -15,6 +15,7 @@ namespace ndgsbp {
 struct DeviceTables {
     int32_t* vcn = nullptr;
     uint32_t* vfirst = nullptr;    // per visit: 1 if it is its CN's first visit in an iteration
+    uint32_t* vdfirst = nullptr;   // per visit (one-lane layout): bit k if edge k writes its VN's first delta slot
     int32_t* visit_ptr = nullptr;  // G + 1
     uint2* fix = nullptr;
     int32_t* fix_ptr = nullptr;    // G + 1

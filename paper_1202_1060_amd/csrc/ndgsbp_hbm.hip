@@ -67,6 +67,15 @@ __device__ __forceinline__ uint64_t claim_slots(const HbmArgs& a, uint64_t want,
     return __ballot(got);
 }
 
+// Sign masks (SGN: the tile keeps, per VN, a 64-bit word in LDS whose bit l
+// is the sign bit of slot l's posterior, i.e. its hard decision): every
+// posterior write updates its VN's word with one ballot, so the syndrome and
+// the hard-decision outputs read LDS instead of the workspace.
+__device__ __forceinline__ void put_sign(uint64_t* sgn, uint32_t v, float x) {
+    const uint64_t m = __ballot(__float_as_uint(x) >> 31);
+    if ((threadIdx.x & 63) == 0) sgn[v] = m;
+}
+
 template <class M, int D, bool UNI>
 __global__ __launch_bounds__(HbmMaxThreads<D>::value) void ndgsbp_hbm_kernel(HbmArgs a) {
     using T = typename M::T;
@@ -75,17 +84,22 @@ __global__ __launch_bounds__(HbmMaxThreads<D>::value) void ndgsbp_hbm_kernel(Hbm
     const Problem& p = a.p;
     const int tid = threadIdx.x, nt = blockDim.x;
     const int lane = tid & 63, wv = tid >> 6, nw = nt >> 6;
+    const bool SGN = a.sgn_lds != 0;
     float* fw = a.fws + (size_t)blockIdx.x * a.fws_tile;
     T* mw = reinterpret_cast<T*>(a.mws) + (size_t)blockIdx.x * a.mws_tile;
+    extern __shared__ __align__(16) uint64_t sgn[];  // n + 2 words when SGN
 
     __shared__ int s_frame[kSlots];   // frame of each slot, -1: none
     __shared__ int s_next[kSlots];    // frame a slot takes after its outputs are written
     __shared__ int s_used[kSlots];    // iterations run on it
     __shared__ int s_fail[kMaxWaves][kSlots];
+    __shared__ unsigned long long s_failm[kMaxWaves];  // SGN: slots a wave saw fail
     __shared__ unsigned long long s_mask[3];  // [0] active, [1] to retire, [2] just filled
     __shared__ unsigned long long s_chk;  // slots that check their syndrome this iteration
     __shared__ int s_more;            // the launch may still have frames
 
+    if (SGN)
+        for (int v = tid; v < p.n + 2; v += nt) sgn[v] = 0ull;  // n + 1: syndrome padding, always 0
     if (wv == 0) {
         if (lane == 0) s_more = 1;
         int f = -1;
@@ -107,8 +121,34 @@ __global__ __launch_bounds__(HbmMaxThreads<D>::value) void ndgsbp_hbm_kernel(Hbm
             const bool mine = (fill >> lane) & 1ull;
             const int f = s_frame[lane];
             const float* y = p.llr + (size_t)(mine ? f : 0) * p.n;
-            for (int v = wv; v < p.n; v += nw)
-                if (mine) fw[(size_t)v * kSlots + lane] = y[v] * kLog2eF + 0.0f;  // -0.0 -> +0.0
+            if ((p.n & 3) == 0 && ((uintptr_t)p.llr & 15u) == 0) {
+                // four consecutive LLRs of the lane's frame per load (rows
+                // of n floats are then 16-byte aligned)
+                for (int q = wv; q < (p.n >> 2); q += nw) {
+                    float4 y4 = make_float4(0.f, 0.f, 0.f, 0.f);
+                    if (mine) y4 = reinterpret_cast<const float4*>(y)[q];
+                    const float x[4] = {y4.x * kLog2eF + 0.0f, y4.y * kLog2eF + 0.0f, y4.z * kLog2eF + 0.0f,
+                                        y4.w * kLog2eF + 0.0f};  // + 0: -0.0 -> +0.0
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        const uint32_t v = 4u * (uint32_t)q + (uint32_t)i;
+                        if (mine) fw[(size_t)v * kSlots + lane] = x[i];
+                        if (SGN) {
+                            const uint64_t neg = __ballot(mine && (__float_as_uint(x[i]) >> 31));
+                            if (lane == 0) sgn[v] = (sgn[v] & ~fill) | neg;
+                        }
+                    }
+                }
+            } else {
+                for (int v = wv; v < p.n; v += nw) {
+                    const float x = mine ? y[v] * kLog2eF + 0.0f : 0.0f;
+                    if (mine) fw[(size_t)v * kSlots + lane] = x;
+                    if (SGN) {
+                        const uint64_t neg = __ballot(mine && (__float_as_uint(x) >> 31));
+                        if (lane == 0) sgn[v] = (sgn[v] & ~fill) | neg;
+                    }
+                }
+            }
             // posterior n: scratch of padding edges; n + 1: 0, syndrome padding
             if (mine && wv == 0) {
                 fw[(size_t)p.n * kSlots + lane] = 0.0f;
@@ -125,6 +165,7 @@ __global__ __launch_bounds__(HbmMaxThreads<D>::value) void ndgsbp_hbm_kernel(Hbm
             for (int j = j0 + wv; j < j1; j += nw) {
                 const int cn = tbl_i32(p.vcn, j);
                 const bool zero_old = fresh && tbl_u32(a.vfirst, j);
+                const uint32_t dfirst = tbl_u32(a.vdfirst, j);
                 float pv[D], lo[D], wvals[D];
                 bool real[D];
                 T st[D];
@@ -145,8 +186,14 @@ __global__ __launch_bounds__(HbmMaxThreads<D>::value) void ndgsbp_hbm_kernel(Hbm
                 cn_core<M, D, UNI, 1>(pv, lo, real, a.ymax, a.cmin, st, wvals);
 #pragma unroll
                 for (int k = 0; k < D; ++k) {
-                    fw[(size_t)ta[k] * (kSlots / 4) + lane] = wvals[k];
+                    // a posterior target takes w; a delta slot takes this
+                    // edge's change w - P, the VN's first slot P + (w - P),
+                    // so that the fix-up only adds its slots in order
+                    float out = wvals[k];
+                    if (ta[k] >= p.ds_start_b) out = (dfirst >> k) & 1u ? pv[k] + (wvals[k] - pv[k]) : wvals[k] - pv[k];
+                    fw[(size_t)ta[k] * (kSlots / 4) + lane] = out;
                     row[k * kSlots] = st[k];
+                    if (SGN && ta[k] < p.ds_start_b) put_sign(sgn, ta[k] >> 2, out);
                 }
             }
             __syncthreads();
@@ -157,10 +204,11 @@ __global__ __launch_bounds__(HbmMaxThreads<D>::value) void ndgsbp_hbm_kernel(Hbm
                     const uint32_t y = tbl_u32(reinterpret_cast<const uint32_t*>(p.fix), 2 * q + 1);
                     const uint32_t v = x & 0xffffu, c = x >> 16;
                     const size_t d0 = ((size_t)(p.ds_start_b >> 2) + y) * kSlots + lane;
-                    const float p0 = fw[(size_t)v * kSlots + lane];
-                    float acc = p0;
-                    for (uint32_t k = 0; k < c; ++k) acc += fw[d0 + (size_t)k * kSlots] - p0;
+                    // P + (w_0 - P) + (w_1 - P) + ..., in slot order
+                    float acc = fw[d0];
+                    for (uint32_t k = 1; k < c; ++k) acc += fw[d0 + (size_t)k * kSlots];
                     fw[(size_t)v * kSlots + lane] = acc;
+                    if (SGN) put_sign(sgn, v, acc);
                 }
                 __syncthreads();
             }
@@ -178,19 +226,57 @@ __global__ __launch_bounds__(HbmMaxThreads<D>::value) void ndgsbp_hbm_kernel(Hbm
         __syncthreads();
         const uint64_t need = s_chk;
         if (need) {
-            // hard decision = sign bit of the posterior (no -0.0 is stored);
-            // a wave stops once every checking slot has failed one of its checks
-            uint32_t x = 0;
-            for (int c = wv; c < p.m; c += nw) {
-                uint32_t par = 0;
-                // entries D .. SD - 1 are padding of every row
+            if (SGN) {
+                // lane l takes check c = 64 i + l of the wave's rounds; a
+                // check's parity word XORs the sign words of its VNs (entries
+                // D .. SD - 1 are padding); a wave stops once every checking
+                // slot has failed some check
+                uint64_t x = 0;
+                for (int c0 = 64 * wv; c0 < p.m; c0 += 64 * nw) {
+                    const int c = c0 + lane;
+                    if (c < p.m) {
+                        const uint4* col = reinterpret_cast<const uint4*>(p.syn_col + (size_t)c * SD);
+                        uint32_t e[SD];
 #pragma unroll
-                for (int k = 0; k < D; ++k)
-                    par ^= __float_as_uint(fw[(size_t)tbl_u32(p.syn_col, (uint32_t)c * SD + k) * (kSlots / 4) + lane]);
-                x |= par;
-                if ((__ballot(x >> 31) & need) == need) break;
+                        for (int q = 0; q < SD / 4; ++q) {
+                            const uint4 w4 = col[q];
+                            e[4 * q] = w4.x;
+                            e[4 * q + 1] = w4.y;
+                            e[4 * q + 2] = w4.z;
+                            e[4 * q + 3] = w4.w;
+                        }
+                        uint64_t par = 0;
+#pragma unroll
+                        for (int k = 0; k < D; ++k) par ^= sgn[e[k] >> 2];
+                        x |= par;
+                    }
+                    uint64_t all = x;
+#pragma unroll
+                    for (int sh = 1; sh < 64; sh <<= 1) {
+                        const uint32_t lo32 = (uint32_t)__shfl_xor((int)(uint32_t)all, sh);
+                        const uint32_t hi32 = (uint32_t)__shfl_xor((int)(uint32_t)(all >> 32), sh);
+                        all |= ((uint64_t)hi32 << 32) | lo32;
+                    }
+                    x = all;
+                    if ((x & need) == need) break;
+                }
+                if (lane == 0) s_failm[wv] = x;
+            } else {
+                // hard decision = sign bit of the posterior (no -0.0 is stored);
+                // a wave stops once every checking slot has failed one of its checks
+                uint32_t x = 0;
+                for (int c = wv; c < p.m; c += nw) {
+                    uint32_t par = 0;
+                    // entries D .. SD - 1 are padding of every row
+#pragma unroll
+                    for (int k = 0; k < D; ++k)
+                        par ^= __float_as_uint(
+                            fw[(size_t)tbl_u32(p.syn_col, (uint32_t)c * SD + k) * (kSlots / 4) + lane]);
+                    x |= par;
+                    if ((__ballot(x >> 31) & need) == need) break;
+                }
+                s_fail[wv][lane] = (int)(x >> 31);
             }
-            s_fail[wv][lane] = (int)(x >> 31);
         }
         __syncthreads();
 
@@ -198,8 +284,13 @@ __global__ __launch_bounds__(HbmMaxThreads<D>::value) void ndgsbp_hbm_kernel(Hbm
         if (wv == 0) {
             const bool act = (active >> lane) & 1ull;
             int fail = 0;
-            if (s_chk)
-                for (int w = 0; w < nw; ++w) fail |= s_fail[w][lane];
+            if (s_chk) {
+                if (SGN) {
+                    for (int w = 0; w < nw; ++w) fail |= (int)((s_failm[w] >> lane) & 1ull);
+                } else {
+                    for (int w = 0; w < nw; ++w) fail |= s_fail[w][lane];
+                }
+            }
             const int used = s_used[lane];
             const bool chk = act && (a.early_stop || used == p.max_iter);
             const bool done = chk && ((a.early_stop && !fail) || used == p.max_iter);
@@ -225,45 +316,83 @@ __global__ __launch_bounds__(HbmMaxThreads<D>::value) void ndgsbp_hbm_kernel(Hbm
             }
         }
         __syncthreads();
-        // outputs of the retired frames, one frame at a time, all lanes
-        uint64_t ret = s_mask[1];
-        while (ret) {
-            const int sl = __ffsll((long long)ret) - 1;
-            ret &= ret - 1;
-            const int f = s_frame[sl];
-            const float* col = fw + sl;
-            float* po = p.post ? p.post + (size_t)f * p.n : nullptr;
-            if (a.packed) {
-                const int nb = (p.n + 7) >> 3;
-                uint8_t* hd = p.hard + (size_t)f * nb;
-                for (int q = tid; q < nb; q += nt) {
-                    uint32_t bits = 0;
+        // outputs of the retired frames
+        const uint64_t retired = s_mask[1];
+        if (retired) {
+            if (SGN) {
+                // hard decisions from the sign words, one frame at a time
+                uint64_t ret = retired;
+                while (ret) {
+                    const int sl = __ffsll((long long)ret) - 1;
+                    ret &= ret - 1;
+                    const int f = s_frame[sl];
+                    if (a.packed) {
+                        const int nb = (p.n + 7) >> 3;
+                        uint8_t* hd = p.hard + (size_t)f * nb;
+                        for (int q = tid; q < nb; q += nt) {
+                            uint32_t bits = 0;
 #pragma unroll
-                    for (int k = 0; k < 8; ++k) {
-                        const int v = 8 * q + k;
-                        if (v < p.n) bits |= (col[(size_t)v * kSlots] < 0.0f ? 1u : 0u) << k;
+                            for (int k = 0; k < 8; ++k) {
+                                const int v = 8 * q + k;
+                                if (v < p.n) bits |= (uint32_t)((sgn[v] >> sl) & 1ull) << k;
+                            }
+                            hd[q] = (uint8_t)bits;
+                        }
+                    } else {
+                        uint8_t* hd = p.hard + (size_t)f * p.n;
+                        for (int v = tid; v < p.n; v += nt) hd[v] = (uint8_t)((sgn[v] >> sl) & 1ull);
                     }
-                    hd[q] = (uint8_t)bits;
                 }
-                if (po)
-                    for (int v = tid; v < p.n; v += nt) po[v] = col[(size_t)v * kSlots] * kLn2F;
+                // posteriors: each row read once, every retiring lane writes its value
+                if (p.post) {
+                    const bool mine = (retired >> lane) & 1ull;
+                    float* po = p.post + (size_t)(mine ? s_frame[lane] : 0) * p.n;
+                    for (int v = wv; v < p.n; v += nw) {
+                        const float x = fw[(size_t)v * kSlots + lane];
+                        if (mine) po[v] = x * kLn2F;
+                    }
+                }
             } else {
-                uint8_t* hd = p.hard + (size_t)f * p.n;
-                for (int v = tid; v < p.n; v += nt) {
-                    const float x = col[(size_t)v * kSlots];
-                    hd[v] = x < 0.0f ? 1 : 0;
-                    if (po) po[v] = x * kLn2F;
+                uint64_t ret = retired;
+                while (ret) {
+                    const int sl = __ffsll((long long)ret) - 1;
+                    ret &= ret - 1;
+                    const int f = s_frame[sl];
+                    const float* col = fw + sl;
+                    float* po = p.post ? p.post + (size_t)f * p.n : nullptr;
+                    if (a.packed) {
+                        const int nb = (p.n + 7) >> 3;
+                        uint8_t* hd = p.hard + (size_t)f * nb;
+                        for (int q = tid; q < nb; q += nt) {
+                            uint32_t bits = 0;
+#pragma unroll
+                            for (int k = 0; k < 8; ++k) {
+                                const int v = 8 * q + k;
+                                if (v < p.n) bits |= (col[(size_t)v * kSlots] < 0.0f ? 1u : 0u) << k;
+                            }
+                            hd[q] = (uint8_t)bits;
+                        }
+                        if (po)
+                            for (int v = tid; v < p.n; v += nt) po[v] = col[(size_t)v * kSlots] * kLn2F;
+                    } else {
+                        uint8_t* hd = p.hard + (size_t)f * p.n;
+                        for (int v = tid; v < p.n; v += nt) {
+                            const float x = col[(size_t)v * kSlots];
+                            hd[v] = x < 0.0f ? 1 : 0;
+                            if (po) po[v] = x * kLn2F;
+                        }
+                    }
                 }
             }
         }
         __syncthreads();
         if (wv == 0) {
             const bool mine = (s_mask[2] >> lane) & 1ull;
-            const bool retired = (s_mask[1] >> lane) & 1ull;
+            const bool ret = (s_mask[1] >> lane) & 1ull;
             if (mine) {
                 s_frame[lane] = s_next[lane];
                 s_used[lane] = 0;
-            } else if (retired) {
+            } else if (ret) {
                 s_frame[lane] = -1;
             }
         }
@@ -286,45 +415,54 @@ hipError_t run_hbm(const HbmArgs& a, int blocks, int threads, hipStream_t s) {
     const void* fn = reinterpret_cast<const void*>(&ndgsbp_hbm_kernel<M, D, UNI>);
     HbmArgs copy = a;
     void* args[] = {&copy};
-    return hipLaunchKernel(fn, dim3(blocks), dim3(threads), args, 0, s);
+    const size_t lds = a.sgn_lds ? hbm_sign_bytes(a.p.n) : 0;
+    if (lds) {
+        const hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    return hipLaunchKernel(fn, dim3(blocks), dim3(threads), args, lds, s);
 }
 
 template <class M, int D, bool UNI>
-hipError_t occ_hbm(int threads, int* out) {
+hipError_t occ_hbm(int threads, size_t lds, int* out) {
     const void* fn = reinterpret_cast<const void*>(&ndgsbp_hbm_kernel<M, D, UNI>);
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(out, fn, threads, 0);
+    if (lds) {
+        const hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(out, fn, threads, lds);
 }
 
 template <class M, int D>
-hipError_t hbm_by_uniform(bool uni, bool launch, const HbmArgs* a, int blocks, int threads, hipStream_t s,
-                          int* out) {
+hipError_t hbm_by_uniform(bool uni, bool launch, const HbmArgs* a, int blocks, int threads, size_t lds,
+                          hipStream_t s, int* out) {
     if (launch) return uni ? run_hbm<M, D, true>(*a, blocks, threads, s) : run_hbm<M, D, false>(*a, blocks, threads, s);
-    return uni ? occ_hbm<M, D, true>(threads, out) : occ_hbm<M, D, false>(threads, out);
+    return uni ? occ_hbm<M, D, true>(threads, lds, out) : occ_hbm<M, D, false>(threads, lds, out);
 }
 
 template <class M>
-hipError_t hbm_by_degree(int D, bool uni, bool launch, const HbmArgs* a, int blocks, int threads, hipStream_t s,
-                         int* out) {
+hipError_t hbm_by_degree(int D, bool uni, bool launch, const HbmArgs* a, int blocks, int threads, size_t lds,
+                         hipStream_t s, int* out) {
     switch (D) {
-        case 4: return hbm_by_uniform<M, 4>(uni, launch, a, blocks, threads, s, out);
-        case 6: return hbm_by_uniform<M, 6>(uni, launch, a, blocks, threads, s, out);
-        case 7: return hbm_by_uniform<M, 7>(uni, launch, a, blocks, threads, s, out);
-        case 8: return hbm_by_uniform<M, 8>(uni, launch, a, blocks, threads, s, out);
-        case 10: return hbm_by_uniform<M, 10>(uni, launch, a, blocks, threads, s, out);
-        case 12: return hbm_by_uniform<M, 12>(uni, launch, a, blocks, threads, s, out);
-        case 16: return hbm_by_uniform<M, 16>(uni, launch, a, blocks, threads, s, out);
-        case 24: return hbm_by_uniform<M, 24>(uni, launch, a, blocks, threads, s, out);
-        case 32: return hbm_by_uniform<M, 32>(uni, launch, a, blocks, threads, s, out);
+        case 4: return hbm_by_uniform<M, 4>(uni, launch, a, blocks, threads, lds, s, out);
+        case 6: return hbm_by_uniform<M, 6>(uni, launch, a, blocks, threads, lds, s, out);
+        case 7: return hbm_by_uniform<M, 7>(uni, launch, a, blocks, threads, lds, s, out);
+        case 8: return hbm_by_uniform<M, 8>(uni, launch, a, blocks, threads, lds, s, out);
+        case 10: return hbm_by_uniform<M, 10>(uni, launch, a, blocks, threads, lds, s, out);
+        case 12: return hbm_by_uniform<M, 12>(uni, launch, a, blocks, threads, lds, s, out);
+        case 16: return hbm_by_uniform<M, 16>(uni, launch, a, blocks, threads, lds, s, out);
+        case 24: return hbm_by_uniform<M, 24>(uni, launch, a, blocks, threads, lds, s, out);
+        case 32: return hbm_by_uniform<M, 32>(uni, launch, a, blocks, threads, lds, s, out);
         default: return hipErrorInvalidValue;
     }
 }
 
 hipError_t hbm_dispatch(MsgKind kind, int D, bool uni, bool launch, const HbmArgs* a, int blocks, int threads,
-                        hipStream_t s, int* out) {
+                        size_t lds, hipStream_t s, int* out) {
     switch (kind) {
-        case kMsgF32: return hbm_by_degree<MsgF32>(D, uni, launch, a, blocks, threads, s, out);
-        case kMsgF16: return hbm_by_degree<MsgF16>(D, uni, launch, a, blocks, threads, s, out);
-        case kMsgBF16: return hbm_by_degree<MsgBF16>(D, uni, launch, a, blocks, threads, s, out);
+        case kMsgF32: return hbm_by_degree<MsgF32>(D, uni, launch, a, blocks, threads, lds, s, out);
+        case kMsgF16: return hbm_by_degree<MsgF16>(D, uni, launch, a, blocks, threads, lds, s, out);
+        case kMsgBF16: return hbm_by_degree<MsgBF16>(D, uni, launch, a, blocks, threads, lds, s, out);
     }
     return hipErrorInvalidValue;
 }
@@ -336,11 +474,13 @@ int hbm_slots() { return kSlots; }
 
 hipError_t launch_hbm(const HbmArgs& a, MsgKind kind, int D, bool uniform, int blocks, int threads,
                       hipStream_t stream) {
-    return hbm_dispatch(kind, D, uniform, true, &a, blocks, threads, stream, nullptr);
+    return hbm_dispatch(kind, D, uniform, true, &a, blocks, threads, 0, stream, nullptr);
 }
 
-hipError_t hbm_occupancy(MsgKind kind, int D, bool uniform, int threads, int* blocks_per_cu) {
-    return hbm_dispatch(kind, D, uniform, false, nullptr, 0, threads, nullptr, blocks_per_cu);
+hipError_t hbm_occupancy(MsgKind kind, int D, bool uniform, int threads, size_t lds_bytes, int* blocks_per_cu) {
+    return hbm_dispatch(kind, D, uniform, false, nullptr, 0, threads, lds_bytes, nullptr, blocks_per_cu);
 }
+
+size_t hbm_sign_bytes(int n) { return (size_t)(n + 2) * 8; }
 
 }  // namespace ndgsbp

@@ -62,6 +62,7 @@ void free_tables(ldpc_code* c) {
     DeviceTables& t = c->dev;
     (void)hipFree(t.vcn);
     (void)hipFree(t.vfirst);
+    (void)hipFree(t.vdfirst);
     (void)hipFree(c->hbm_ws);
     c->hbm_ws = nullptr;
     c->hbm_ws_bytes = 0;
@@ -655,8 +656,11 @@ hipError_t launch_classes(const std::vector<BatchClass>& classes, MsgKind kind, 
 
 // Staging ring of the asynchronous ldpc_decode_batched, one per device, kept
 // for the life of the process: each slot holds a pinned host and a device
-// copy of a problem table, work counters and fork/join events; a slot is
-// reused once the call that last used it has finished on the device.
+// copy of a problem table, work counters, fork/join events and the streams
+// its launch classes fork onto (per slot, so that calls in flight at the
+// same time, e.g. from a serving loop on several caller streams, do not
+// queue behind each other's classes); a slot is reused once the call that
+// last used it has finished on the device.
 constexpr int kStageRing = 16;
 constexpr int kStageClasses = 64;
 constexpr int kStageStreams = 4;
@@ -668,6 +672,7 @@ struct StageSlot {
     uint32_t* work = nullptr; // 2 per class, zero between launches
     hipEvent_t done = nullptr;
     std::vector<hipEvent_t> fork_join;
+    std::vector<hipStream_t> streams;  // kStageStreams - 1 fork streams
     bool in_use = false;
 };
 
@@ -675,7 +680,6 @@ struct DeviceStage {
     std::mutex mu;
     StageSlot slots[kStageRing];
     unsigned next = 0;
-    std::vector<hipStream_t> streams;  // kStageStreams - 1 extra streams
 };
 
 std::mutex g_stage_mu;
@@ -690,12 +694,12 @@ hipError_t get_stage(int device, DeviceStage** out) {
     }
     DeviceStage* ds = new DeviceStage();
     hipError_t e = hipSuccess;
-    for (int k = 1; k < kStageStreams && e == hipSuccess; ++k) {
-        hipStream_t st = nullptr;
-        e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
-        if (e == hipSuccess) ds->streams.push_back(st);
-    }
     for (StageSlot& s : ds->slots) {
+        for (int k = 1; k < kStageStreams && e == hipSuccess; ++k) {
+            hipStream_t st = nullptr;
+            e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
+            if (e == hipSuccess) s.streams.push_back(st);
+        }
         if (e == hipSuccess) e = hipEventCreateWithFlags(&s.done, hipEventDisableTiming);
         for (int k = 0; k < kStageStreams && e == hipSuccess; ++k) {
             hipEvent_t ev = nullptr;
@@ -728,8 +732,11 @@ int decode_hbm(ldpc_code* c, const float* llr, int32_t num_frames, int32_t max_i
     const int slots = hbm_slots();
     const int waves = std::max(1, std::min(hbm_max_threads(lay.D) / 64, c->max_group_visits));
     const int threads = 64 * waves;
+    // the tile's sign words live in LDS when they fit
+    const size_t sgn_bytes = hbm_sign_bytes(c->n);
+    const bool sgn = sgn_bytes <= c->max_lds - kHbmStaticLds;
     int per_cu = 0;
-    hipError_t e = hbm_occupancy(kind, lay.D, lay.uniform, threads, &per_cu);
+    hipError_t e = hbm_occupancy(kind, lay.D, lay.uniform, threads, sgn ? sgn_bytes : 0, &per_cu);
     if (e != hipSuccess) return hip_fail(e, "occupancy query (HBM tier)");
     if (per_cu < 1) return fail(LDPC_EUNSUPPORTED, "HBM-tier kernel cannot be resident");
     const int64_t tiles_needed = (num_frames + slots - 1) / slots;
@@ -744,6 +751,8 @@ int decode_hbm(ldpc_code* c, const float* llr, int32_t num_frames, int32_t max_i
     HbmArgs a{};
     a.p = make_problem(c, lay, llr, num_frames, max_iter, hard, post, iters, syn_ok);
     a.vfirst = c->dev.vfirst;
+    a.vdfirst = c->dev.vdfirst;
+    a.sgn_lds = sgn ? 1 : 0;
     a.fws_tile = ftile_bytes / 4;
     a.mws_tile = mws_tile;
     a.early_stop = (flags & LDPC_FLAG_EARLY_STOP) ? 1 : 0;
@@ -927,6 +936,7 @@ int ldpc_code_create(const ldpc_h_csr* H, const ldpc_grouping* grouping, int32_t
     // visits, edge source/target indices and fix-up tables (mapping-free)
     std::vector<int32_t> vcn;
     std::vector<uint32_t> esrc, edst;  // per visit edge, in row order
+    std::vector<uint8_t> efirst;       // per visit edge: it writes its VN's first delta slot
     std::vector<int32_t> vdeg_of(1, 0);  // prefix over visits of their degree
     std::vector<int32_t> visit_ptr(1, 0), fix_ptr(1, 0);
     std::vector<uint2> fix;
@@ -969,9 +979,11 @@ int ldpc_code_create(const ldpc_h_csr* H, const ldpc_grouping* grouping, int32_t
             for (int32_t k = 0; k < d; ++k) {
                 const int32_t v = H->col_idx[b + k];
                 // input-only edges add back into the scratch word n
-                const int32_t tgt = input_only(v) ? n : cnt[v] >= 2 ? ds_start + first_slot[v] + next_fill[v]++ : v;
+                const bool multi = !input_only(v) && cnt[v] >= 2;
+                const int32_t tgt = input_only(v) ? n : multi ? ds_start + first_slot[v] + next_fill[v]++ : v;
                 esrc.push_back((uint32_t)v);
                 edst.push_back((uint32_t)tgt);
+                efirst.push_back(multi && next_fill[v] == 1 ? 1 : 0);
                 outputs += input_only(v) ? 0 : 1;
             }
             vdeg_of.push_back(vdeg_of.back() + d);
@@ -993,6 +1005,7 @@ int ldpc_code_create(const ldpc_h_csr* H, const ldpc_grouping* grouping, int32_t
 
     // per-mapping tables: edge half-records padded to D, syndrome rows
     std::vector<uint32_t> vw_h[4], syn_h[4];
+    std::vector<uint32_t> vdfirst;  // one-lane layout: bit k = edge at position k writes a first delta slot
     std::vector<int32_t> order_h[4];  // per mapping: row position -> edge of the CN
     for (int h : {1, 2, 4}) {
         Layout& l = c->lay[h - 1];
@@ -1010,6 +1023,7 @@ int ldpc_code_create(const ldpc_h_csr* H, const ldpc_grouping* grouping, int32_t
         edge_order(H, h, D, vcn, visit_ptr, order);
         std::vector<uint32_t>& vw = vw_h[h - 1];
         vw.assign(vcn.size() * (size_t)h * W, 0u);
+        if (h == 1) vdfirst.assign(vcn.size(), 0u);
         for (size_t j = 0; j < vcn.size(); ++j) {
             const int32_t e0 = vdeg_of[j], d = vdeg_of[j + 1] - e0;
             for (int k = 0; k < D; ++k) {
@@ -1018,6 +1032,7 @@ int ldpc_code_create(const ldpc_h_csr* H, const ldpc_grouping* grouping, int32_t
                 if (q >= 0) {
                     src = 4u * esrc[e0 + q];
                     dst = 4u * edst[e0 + q];
+                    if (h == 1 && efirst[e0 + q]) vdfirst[j] |= 1u << k;
                 }
                 const size_t half = (j * h + (size_t)(k / DH)) * W;
                 vw[half + k % DH] = src;
@@ -1085,6 +1100,7 @@ int ldpc_code_create(const ldpc_h_csr* H, const ldpc_grouping* grouping, int32_t
     }
     if (e == hipSuccess) e = upload(&c->dev.vcn, vcn);
     if (e == hipSuccess) e = upload(&c->dev.vfirst, vfirst);
+    if (e == hipSuccess) e = upload(&c->dev.vdfirst, vdfirst);
     if (e == hipSuccess) e = upload(&c->dev.visit_ptr, visit_ptr);
     if (e == hipSuccess) e = upload(&c->dev.fix, fix);
     if (e == hipSuccess) e = upload(&c->dev.fix_ptr, fix_ptr);
@@ -1311,7 +1327,7 @@ int ldpc_decode_batched(const ldpc_problem* probs, int32_t count, uint32_t flags
     for (size_t k = 0; k < plan.classes.size(); ++k)
         finish_class_args(plan.classes[k], plan.table, slot.dev, slot.work + 2 * k, flags);
     const int ns = std::min<int>(kStageStreams, (int)plan.classes.size());
-    std::vector<hipStream_t> extra(ds->streams.begin(), ds->streams.begin() + (ns - 1));
+    std::vector<hipStream_t> extra(slot.streams.begin(), slot.streams.begin() + (ns - 1));
     std::vector<hipEvent_t> evs(slot.fork_join.begin(), slot.fork_join.begin() + ns);
     if (e == hipSuccess) e = launch_classes(plan.classes, kind, main, extra, evs);
     if (e == hipSuccess) e = hipEventRecord(slot.done, main);

@@ -15,12 +15,12 @@ of one code. Two policies share the request bookkeeping:
   stream, with FP32 messages (the reference policy).
 
 Memory: an admitted request holds its outputs (hard decisions, iteration
-count, syndrome flag, and with ``posteriors`` the total LLRs) in device
-memory until its launch completes; the
-budget caps the bytes held by requests in flight. Request LLRs are device
-buffers owned by the caller (the request's ``llr`` address); code tables
-and message state stay on the device (messages live in LDS for the whole
-decode of a frame).
+count, syndrome flag, and with ``posteriors`` the total LLRs) and, when its
+LLRs arrive in host memory, their device copy, until its launch completes;
+the budget caps the bytes held by requests in flight. Request LLRs are
+either device buffers owned by the caller or a pinned host buffer that the
+server stages per launch (``Requests``); code tables and message state stay
+on the device (messages live in LDS for the whole decode of a frame).
 
 Times are host wall-clock: a request is done when the host sees the event
 recorded after its launch complete; latency = done - arrival.
@@ -46,16 +46,30 @@ assert ctypes.sizeof(_native.ldpc_problem) == PROBLEM_DTYPE.itemsize
 
 class Requests:
     """A request stream as arrays: arrival time (s, nondecreasing), code
-    index, frame count, device address of the request's LLRs ([frames][n]
-    float32) and iteration cap."""
+    index, frame count, the request's LLRs and iteration cap.
 
-    def __init__(self, arrival, code, frames, llr_addr, max_iter):
+    LLRs either sit in device memory already (``llr_addr``: device address
+    of [frames][n] float32 per request) or arrive in host memory
+    (``host_llr``: a pinned 1-D CPU tensor, float32 or float16, holding every
+    request's [frames][n] LLRs back to back in arrival order, request i at
+    elements ``host_off[i] .. host_off[i+1]``); the server then copies each
+    admitted group of requests to the device with one asynchronous copy on
+    its launch stream (widening 16-bit LLRs to float32 there), so staging is
+    part of every request's latency."""
+
+    def __init__(self, arrival, code, frames, llr_addr, max_iter, host_llr=None, host_off=None):
         self.arrival = np.asarray(arrival, dtype=np.float64)
         self.code = np.asarray(code, dtype=np.int64)
         self.frames = np.asarray(frames, dtype=np.int64)
-        self.llr_addr = np.asarray(llr_addr, dtype=np.uint64)
+        self.llr_addr = None if llr_addr is None else np.asarray(llr_addr, dtype=np.uint64)
         self.max_iter = np.asarray(max_iter, dtype=np.int32)
+        self.host_llr = host_llr
+        self.host_off = None if host_off is None else np.asarray(host_off, dtype=np.int64)
         assert np.all(np.diff(self.arrival) >= 0)
+        assert (self.llr_addr is None) != (host_llr is None), "give llr_addr or host_llr"
+        if host_llr is not None:
+            assert host_llr.dim() == 1 and host_llr.dtype in (torch.float32, torch.float16)
+            assert len(self.host_off) == len(self.arrival) + 1
 
     def __len__(self):
         return len(self.arrival)
@@ -82,8 +96,12 @@ class Server:
 
     def request_bytes(self, req: Requests):
         """Device bytes a request holds while in flight: its outputs (hard
-        decisions, iteration count, syndrome flag, and posteriors if kept)."""
+        decisions, iteration count, syndrome flag, and posteriors if kept)
+        and, for LLRs staged from host memory, their device copy (plus the
+        float32 widening of 16-bit LLRs)."""
         per_bit = 5 if self.posteriors else 1
+        if req.host_llr is not None:
+            per_bit += 4 if req.host_llr.dtype == torch.float32 else 6
         return req.frames * (self.n[req.code] * per_bit + 4 + 1)
 
     def run(self, req: Requests, *, keep_results=False, clock=time.perf_counter):
@@ -155,7 +173,18 @@ class Server:
         n = self.n[req.code[a:b]]
         hard_off = np.concatenate([[0], np.cumsum(F * n)])
         it_off = np.concatenate([[0], np.cumsum(F)])
+        staged = None
         with torch.cuda.stream(stream):
+            if req.host_llr is not None:
+                # one copy of the group's LLRs (contiguous in host memory),
+                # widened to float32 on the device
+                h0, h1 = int(req.host_off[a]), int(req.host_off[b])
+                dev_in = torch.empty(h1 - h0, dtype=req.host_llr.dtype, device=self.device)
+                dev_in.copy_(req.host_llr[h0:h1], non_blocking=True)
+                staged = dev_in if dev_in.dtype == torch.float32 else dev_in.float()
+                llr_addr = np.uint64(staged.data_ptr()) + (4 * (req.host_off[a:b] - h0)).astype(np.uint64)
+            else:
+                llr_addr = req.llr_addr[a:b]
             hard = torch.empty(int(hard_off[-1]), dtype=torch.uint8, device=self.device)
             iters = torch.empty(int(it_off[-1]), dtype=torch.int32, device=self.device)
             syn = torch.empty(int(it_off[-1]), dtype=torch.uint8, device=self.device)
@@ -163,7 +192,7 @@ class Server:
                 if self.posteriors else None
         probs = np.zeros(b - a, dtype=PROBLEM_DTYPE)
         probs["code"] = self.handles[req.code[a:b]]
-        probs["llr"] = req.llr_addr[a:b]
+        probs["llr"] = llr_addr
         probs["num_frames"] = F
         probs["max_iter"] = req.max_iter[a:b]
         probs["hard"] = np.uint64(hard.data_ptr()) + hard_off[:-1].astype(np.uint64)
@@ -184,11 +213,11 @@ class Server:
         _native.check(rc)
         ev = torch.cuda.Event()
         ev.record(stream)
-        return ev, (hard, iters, syn, post, hard_off, it_off, n)
+        return ev, (hard, iters, syn, post, hard_off, it_off, n, staged)
 
     @staticmethod
     def _keep(results, req, a, b, bufs):
-        hard, iters, syn, post, hard_off, it_off, n = bufs
+        hard, iters, syn, post, hard_off, it_off, n, _ = bufs
         h, it, sy = hard.cpu().numpy(), iters.cpu().numpy(), syn.cpu().numpy()
         po = post.cpu().numpy() if post is not None else None
         for j in range(b - a):
