@@ -83,11 +83,16 @@ __global__ __launch_bounds__(HbmMaxThreads<D>::value) void ndgsbp_hbm_kernel(Hbm
     constexpr int W = (2 * D + 3) / 4 * 4;  // words per visit record (one lane per CN)
     const Problem& p = a.p;
     const int tid = threadIdx.x, nt = blockDim.x;
-    const int lane = tid & 63, wv = tid >> 6, nw = nt >> 6;
+    // the wave index is wave-uniform: visit indices built from it stay in
+    // scalar registers, so the visit records come through scalar loads
+    const int lane = tid & 63, wv = __builtin_amdgcn_readfirstlane(tid >> 6), nw = nt >> 6;
     const bool SGN = a.sgn_lds != 0;
+    const bool DL = a.dslot_lds != 0;
     float* fw = a.fws + (size_t)blockIdx.x * a.fws_tile;
     T* mw = reinterpret_cast<T*>(a.mws) + (size_t)blockIdx.x * a.mws_tile;
     extern __shared__ __align__(16) uint64_t sgn[];  // n + 2 words when SGN
+    // delta slot s of slot l at dsl[s * 64 + l] when DL (after the sign words)
+    float* dsl = reinterpret_cast<float*>(sgn + (SGN ? p.n + 2 : 0));
 
     __shared__ int s_frame[kSlots];   // frame of each slot, -1: none
     __shared__ int s_next[kSlots];    // frame a slot takes after its outputs are written
@@ -178,9 +183,13 @@ __global__ __launch_bounds__(HbmMaxThreads<D>::value) void ndgsbp_hbm_kernel(Hbm
                 T* row = mw + (size_t)cn * D * kSlots + lane;
 #pragma unroll
                 for (int k = 0; k < D; ++k) {
-                    // byte offset 4r of float row r -> element r * 64
+                    // byte offset 4r of float row r -> element r * 64; the
+                    // message row is loaded for every slot (a fresh slot's
+                    // bits are replaced by 0), so that no load waits on a
+                    // branch
                     pv[k] = fw[(size_t)pa[k] * (kSlots / 4) + lane];
-                    lo[k] = zero_old ? 0.0f : M::unpack(row[k * kSlots]);
+                    const float old = M::unpack(row[k * kSlots]);
+                    lo[k] = zero_old ? 0.0f : old;
                     real[k] = pa[k] != p.pad_b;
                 }
                 cn_core<M, D, UNI, 1>(pv, lo, real, a.ymax, a.cmin, st, wvals);
@@ -189,11 +198,17 @@ __global__ __launch_bounds__(HbmMaxThreads<D>::value) void ndgsbp_hbm_kernel(Hbm
                     // a posterior target takes w; a delta slot takes this
                     // edge's change w - P, the VN's first slot P + (w - P),
                     // so that the fix-up only adds its slots in order
-                    float out = wvals[k];
-                    if (ta[k] >= p.ds_start_b) out = (dfirst >> k) & 1u ? pv[k] + (wvals[k] - pv[k]) : wvals[k] - pv[k];
-                    fw[(size_t)ta[k] * (kSlots / 4) + lane] = out;
+                    if (ta[k] >= p.ds_start_b) {
+                        const float out = (dfirst >> k) & 1u ? pv[k] + (wvals[k] - pv[k]) : wvals[k] - pv[k];
+                        if (DL)
+                            dsl[((ta[k] - p.ds_start_b) >> 2) * kSlots + lane] = out;
+                        else
+                            fw[(size_t)ta[k] * (kSlots / 4) + lane] = out;
+                    } else {
+                        fw[(size_t)ta[k] * (kSlots / 4) + lane] = wvals[k];
+                        if (SGN) put_sign(sgn, ta[k] >> 2, wvals[k]);
+                    }
                     row[k * kSlots] = st[k];
-                    if (SGN && ta[k] < p.ds_start_b) put_sign(sgn, ta[k] >> 2, out);
                 }
             }
             __syncthreads();
@@ -203,10 +218,17 @@ __global__ __launch_bounds__(HbmMaxThreads<D>::value) void ndgsbp_hbm_kernel(Hbm
                     const uint32_t x = tbl_u32(reinterpret_cast<const uint32_t*>(p.fix), 2 * q);
                     const uint32_t y = tbl_u32(reinterpret_cast<const uint32_t*>(p.fix), 2 * q + 1);
                     const uint32_t v = x & 0xffffu, c = x >> 16;
-                    const size_t d0 = ((size_t)(p.ds_start_b >> 2) + y) * kSlots + lane;
                     // P + (w_0 - P) + (w_1 - P) + ..., in slot order
-                    float acc = fw[d0];
-                    for (uint32_t k = 1; k < c; ++k) acc += fw[d0 + (size_t)k * kSlots];
+                    float acc;
+                    if (DL) {
+                        const uint32_t d0 = y * kSlots + lane;
+                        acc = dsl[d0];
+                        for (uint32_t k = 1; k < c; ++k) acc += dsl[d0 + k * kSlots];
+                    } else {
+                        const size_t d0 = ((size_t)(p.ds_start_b >> 2) + y) * kSlots + lane;
+                        acc = fw[d0];
+                        for (uint32_t k = 1; k < c; ++k) acc += fw[d0 + (size_t)k * kSlots];
+                    }
                     fw[(size_t)v * kSlots + lane] = acc;
                     if (SGN) put_sign(sgn, v, acc);
                 }
@@ -415,7 +437,7 @@ hipError_t run_hbm(const HbmArgs& a, int blocks, int threads, hipStream_t s) {
     const void* fn = reinterpret_cast<const void*>(&ndgsbp_hbm_kernel<M, D, UNI>);
     HbmArgs copy = a;
     void* args[] = {&copy};
-    const size_t lds = a.sgn_lds ? hbm_sign_bytes(a.p.n) : 0;
+    const size_t lds = (a.sgn_lds ? hbm_sign_bytes(a.p.n) : 0) + (a.dslot_lds ? hbm_slot_bytes(a.max_slots) : 0);
     if (lds) {
         const hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
@@ -482,5 +504,6 @@ hipError_t hbm_occupancy(MsgKind kind, int D, bool uniform, int threads, size_t 
 }
 
 size_t hbm_sign_bytes(int n) { return (size_t)(n + 2) * 8; }
+size_t hbm_slot_bytes(int max_slots) { return (size_t)max_slots * kSlots * 4; }
 
 }  // namespace ndgsbp

@@ -732,11 +732,15 @@ int decode_hbm(ldpc_code* c, const float* llr, int32_t num_frames, int32_t max_i
     const int slots = hbm_slots();
     const int waves = std::max(1, std::min(hbm_max_threads(lay.D) / 64, c->max_group_visits));
     const int threads = 64 * waves;
-    // the tile's sign words live in LDS when they fit
+    // the tile's sign words live in LDS when they fit, and its delta slots
+    // too when both fit
     const size_t sgn_bytes = hbm_sign_bytes(c->n);
+    const size_t slot_bytes = hbm_slot_bytes(c->max_slots);
     const bool sgn = sgn_bytes <= c->max_lds - kHbmStaticLds;
+    const bool dl = sgn && sgn_bytes + slot_bytes <= c->max_lds - kHbmStaticLds;
+    const size_t lds = (sgn ? sgn_bytes : 0) + (dl ? slot_bytes : 0);
     int per_cu = 0;
-    hipError_t e = hbm_occupancy(kind, lay.D, lay.uniform, threads, sgn ? sgn_bytes : 0, &per_cu);
+    hipError_t e = hbm_occupancy(kind, lay.D, lay.uniform, threads, lds, &per_cu);
     if (e != hipSuccess) return hip_fail(e, "occupancy query (HBM tier)");
     if (per_cu < 1) return fail(LDPC_EUNSUPPORTED, "HBM-tier kernel cannot be resident");
     const int64_t tiles_needed = (num_frames + slots - 1) / slots;
@@ -753,6 +757,8 @@ int decode_hbm(ldpc_code* c, const float* llr, int32_t num_frames, int32_t max_i
     a.vfirst = c->dev.vfirst;
     a.vdfirst = c->dev.vdfirst;
     a.sgn_lds = sgn ? 1 : 0;
+    a.dslot_lds = dl ? 1 : 0;
+    a.max_slots = c->max_slots;
     a.fws_tile = ftile_bytes / 4;
     a.mws_tile = mws_tile;
     a.early_stop = (flags & LDPC_FLAG_EARLY_STOP) ? 1 : 0;

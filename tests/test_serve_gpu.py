@@ -116,3 +116,36 @@ def test_served_fp32_meets_the_oracle_bar(setup):
         got = out["results"][i]
         compare(dict(hard=got["hard"], post=got["post"], iters=got["iters"], syn_ok=got["syn_ok"]), ref)
     assert seen == {0, 1, 2}
+
+
+@pytest.mark.parametrize("dtype", ["float32", "float16"])
+def test_staged_from_host_equals_alone(setup, dtype):
+    """Request LLRs in pinned host memory, staged per launch (one copy of
+    each admitted group, 16-bit LLRs widened on the device): every request's
+    outputs equal its single decode of the same (widened) LLRs, with arrivals
+    spread in time, and the staged bytes count against the budget."""
+    s = setup
+    r = s["r"]
+    N = 120
+    parts = []
+    for i in range(N):
+        c, b, o, F = int(r["code"][i]), int(r["bin"][i]), int(s["off"][i]), int(r["frames"][i])
+        parts.append(s["pools"][c][0][b, o:o + F].reshape(-1))
+    flat = np.concatenate(parts)
+    host = torch.empty(flat.size, dtype=getattr(torch, dtype), pin_memory=True)
+    host.copy_(torch.from_numpy(flat))
+    off = np.concatenate([[0], np.cumsum([p.size for p in parts])])
+    req = Requests(r["arrival"][:N] / 20000.0, r["code"][:N], r["frames"][:N], None,
+                   np.full(N, 20, dtype=np.int32), host_llr=host, host_off=off)
+    srv = Server(s["codes"], policy="batched", msg="fp16", budget_bytes=8 << 20, max_inflight=3)
+    need = srv.request_bytes(req)
+    per_bit = 1 + (4 if dtype == "float32" else 6)
+    assert np.array_equal(need, r["frames"][:N] * (np.array([c.n for c in s["codes"]])[r["code"][:N]] * per_bit + 5))
+    out = srv.run(req, keep_results=True)
+    assert out["launches"] < N
+    for i in range(N):
+        c, F = int(r["code"][i]), int(r["frames"][i])
+        llr = host[off[i]:off[i + 1]].float().numpy().reshape(F, -1)
+        want = gpu_decode(s["codes"][c], llr, 20, True, "fp16")
+        for k in ("hard", "iters", "syn_ok"):
+            assert np.array_equal(out["results"][i][k], want[k]), (i, k)
