@@ -62,7 +62,8 @@ def _load():
                                             ctypes.c_int, ctypes.POINTER(ctypes.c_float), ctypes.c_int,
                                             ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_double),
                                             ctypes.POINTER(ctypes.c_uint8), i32p,
-                                            ctypes.POINTER(ctypes.c_uint8), ctypes.c_int]
+                                            ctypes.POINTER(ctypes.c_uint8), ctypes.POINTER(ctypes.c_double),
+                                            ctypes.c_int]
         lib.ref_decode_vertical.restype = ctypes.c_int
         lib.ref_decode_vertical.argtypes = lib.ref_decode.argtypes
         lib.ref_phi_f64.restype = ctypes.c_double
@@ -117,7 +118,12 @@ def decode(code, groups, llr, max_iter: int, early_stop: bool, nthreads: int = 0
     form blocks of Gp and iteration l uses block (l-1) mod (len(groups)/Gp)
     (a new grouping every iteration, Step 4 back to Step 1). Returns
     dict(post=float64 (F,n), hard=uint8 (F,n), iters=int32 (F,),
-    syn_ok=uint8 (F,), threads=int)."""
+    syn_ok=uint8 (F,), margin=float64 (F,), threads=int); ``margin`` is
+    the stop margin: the smallest change of total LLRs that could move the
+    iteration at which the syndrome test of Step 4 stops the frame (minimum
+    over iterations of: with a zero syndrome, the smallest |P| of a VN in
+    some check; otherwise the largest over failing checks of the smallest
+    |P| in the check)."""
     lib = _load()
     llr = np.ascontiguousarray(llr, dtype=np.float32)
     if llr.ndim == 1:
@@ -131,15 +137,16 @@ def decode(code, groups, llr, max_iter: int, early_stop: bool, nthreads: int = 0
     hard = np.zeros((F, n), dtype=np.uint8)
     iters = np.zeros(F, dtype=np.int32)
     syn = np.zeros(F, dtype=np.uint8)
+    margin = np.zeros(F, dtype=np.float64)
     i32 = ctypes.c_int32
     rc = lib.ref_decode_schedule(code.m, n, _p(row_ptr, i32), _p(col, i32), len(groups), _p(gptr, i32),
                         _p(gcn, i32), int(groups_per_iteration), _p(llr, ctypes.c_float), F, int(max_iter),
                         int(bool(early_stop)),
                         _p(post, ctypes.c_double), _p(hard, ctypes.c_uint8), _p(iters, i32),
-                        _p(syn, ctypes.c_uint8), int(nthreads))
+                        _p(syn, ctypes.c_uint8), _p(margin, ctypes.c_double), int(nthreads))
     if rc < 0:
         raise ValueError(f"ref_decode rejected its input ({rc})")
-    return dict(post=post, hard=hard, iters=iters, syn_ok=syn, threads=rc)
+    return dict(post=post, hard=hard, iters=iters, syn_ok=syn, margin=margin, threads=rc)
 
 
 def decode_vertical(code, vn_groups, llr, max_iter: int, early_stop: bool, nthreads: int = 0):
@@ -201,6 +208,21 @@ def decode_with_sensitivity(code, groups, llr, max_iter: int, early_stop: bool, 
     flip = np.any(ctl["hard"] != ref["hard"], axis=1) | (ctl["iters"] != ref["iters"])
     sens[flip] = np.inf
     ref["sens"] = sens
+    llr = np.ascontiguousarray(llr, dtype=np.float32).reshape(-1, code.n)
+
+    def rerun(frames, iters):
+        """Posteriors of the given frames after exactly iters[i] iterations
+        (no early stop): the oracle's result at another stop iteration."""
+        frames = np.asarray(frames, dtype=np.int64)
+        iters = np.asarray(iters, dtype=np.int64)
+        out = np.zeros((len(frames), code.n))
+        for it in np.unique(iters):
+            sel = np.nonzero(iters == it)[0]
+            out[sel] = decode(code, groups, llr[frames[sel]], int(it), False, nthreads,
+                              groups_per_iteration)["post"]
+        return out
+
+    ref["rerun"] = rerun
     return ref
 
 

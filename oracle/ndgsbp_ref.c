@@ -78,6 +78,7 @@ typedef struct {
     uint8_t* hard;
     int32_t* iters;
     uint8_t* syn_ok;
+    double* margin; /* F: smallest |total LLR| over VNs in the last two iterations run */
     int nthreads;
     int gper; /* groups per iteration: iteration l uses block (l-1) mod (G / gper) */
     int vertical; /* groups hold VN ids: the vertical group-shuffled schedule */
@@ -100,6 +101,9 @@ static void decode_frame(const ref_job* J, int f, double* Lch, double* Lcv, doub
     for (int n = 0; n < N; ++n) stamp[n] = -1;
     int used = J->max_iter, ok = 0;
     int visit = 0;
+    /* stop margin: the smallest change of total LLRs that could change the
+       iteration at which Step 4 stops the frame (see run_job) */
+    double margin = INFINITY;
     const int R = J->G / J->gper;
     for (int l = 1; l <= J->max_iter; ++l) {
         const int g0 = ((l - 1) % R) * J->gper;
@@ -167,13 +171,28 @@ static void decode_frame(const ref_job* J, int f, double* Lch, double* Lcv, doub
             for (int a = J->vptr[n]; a < J->vptr[n + 1]; ++a) s += Lcv[J->vedge[a]];
             P[n] = s;
         }
-        /* Step 4: hard decision and syndrome over all M checks */
+        /* Step 4: hard decision and syndrome over all M checks. Beside it,
+           for the stop margin: with a zero syndrome, the smallest |P| of a
+           VN in some check (a flip there would fail a check); otherwise the
+           largest, over failing checks, of the smallest |P| in the check (a
+           zero syndrome needs a flip in every failing check). */
         ok = 1;
-        for (int m = 0; m < M && ok; ++m) {
+        double firm_fail = 0.0, weakest = INFINITY;
+        for (int m = 0; m < M; ++m) {
             int par = 0;
-            for (int e = J->row_ptr[m]; e < J->row_ptr[m + 1]; ++e) par ^= (P[J->col[e]] < 0.0);
-            if (par) ok = 0;
+            double low = INFINITY;
+            for (int e = J->row_ptr[m]; e < J->row_ptr[m + 1]; ++e) {
+                par ^= (P[J->col[e]] < 0.0);
+                if (fabs(P[J->col[e]]) < low) low = fabs(P[J->col[e]]);
+            }
+            if (par) {
+                ok = 0;
+                if (low > firm_fail) firm_fail = low;
+            }
+            if (low < weakest) weakest = low;
         }
+        const double here = ok ? weakest : firm_fail;
+        if (here < margin) margin = here;
         if (J->early_stop && ok) {
             used = l;
             break;
@@ -184,6 +203,7 @@ static void decode_frame(const ref_job* J, int f, double* Lch, double* Lcv, doub
         for (int n = 0; n < N; ++n) J->hard[(size_t)f * N + n] = (uint8_t)(P[n] < 0.0);
     if (J->iters) J->iters[f] = used;
     if (J->syn_ok) J->syn_ok[f] = (uint8_t)ok;
+    if (J->margin) J->margin[f] = margin;
 }
 
 static void* worker(void* arg) {
@@ -218,12 +238,18 @@ static void* worker(void* arg) {
  * grouping every iteration, cycling through G / gper of them (Step 4 returns
  * to the grouping of Step 1); gper = 0 means all G groups every iteration.
  * Outputs (each may be NULL): post F x N doubles, hard F x N bytes,
- * iters F ints, syn_ok F bytes. nthreads <= 0 uses every online CPU.
+ * iters F ints, syn_ok F bytes, margin F doubles. margin is a diagnostic
+ * for the test bar: the smallest change of the total LLRs of eq. (3) that
+ * could move the iteration at which Step 4 stops, i.e. the minimum over the
+ * iterations run of: with a zero syndrome, the smallest |P| of a VN in some
+ * check; with a nonzero one, the largest over failing checks of the
+ * smallest |P| in that check. nthreads <= 0 uses every online CPU.
  * Returns the number of threads used, or a negative value on bad input.
  */
 static int run_job(int M, int N, const int32_t* row_ptr, const int32_t* col, int G, const int32_t* gptr,
                    const int32_t* gcn, int gper, int vertical, const float* llr, int F, int max_iter,
-                   int early_stop, double* post, uint8_t* hard, int32_t* iters, uint8_t* syn_ok, int nthreads) {
+                   int early_stop, double* post, uint8_t* hard, int32_t* iters, uint8_t* syn_ok, double* margin,
+                   int nthreads) {
     if (M <= 0 || N <= 0 || G <= 0 || F < 0 || max_iter < 1) return -1;
     if (gper == 0) gper = G;
     if (gper < 0 || G % gper) return -1;
@@ -240,7 +266,7 @@ static int run_job(int M, int N, const int32_t* row_ptr, const int32_t* col, int
     J.M = M; J.N = N; J.E = E; J.G = G; J.gper = gper; J.vertical = vertical;
     J.row_ptr = row_ptr; J.col = col; J.gptr = gptr; J.gcn = gcn;
     J.llr = llr; J.F = F; J.max_iter = max_iter; J.early_stop = early_stop;
-    J.post = post; J.hard = hard; J.iters = iters; J.syn_ok = syn_ok;
+    J.post = post; J.hard = hard; J.iters = iters; J.syn_ok = syn_ok; J.margin = margin;
     /* VN -> edge adjacency (M(n)), edges listed in increasing edge id */
     J.vptr = calloc((size_t)N + 1, sizeof(int32_t));
     J.vedge = malloc(sizeof(int32_t) * (E + 1));
@@ -281,9 +307,10 @@ static int run_job(int M, int N, const int32_t* row_ptr, const int32_t* col, int
 
 int ref_decode_schedule(int M, int N, const int32_t* row_ptr, const int32_t* col, int G, const int32_t* gptr,
                         const int32_t* gcn, int gper, const float* llr, int F, int max_iter, int early_stop,
-                        double* post, uint8_t* hard, int32_t* iters, uint8_t* syn_ok, int nthreads) {
+                        double* post, uint8_t* hard, int32_t* iters, uint8_t* syn_ok, double* margin,
+                        int nthreads) {
     return run_job(M, N, row_ptr, col, G, gptr, gcn, gper, 0, llr, F, max_iter, early_stop, post, hard, iters,
-                   syn_ok, nthreads);
+                   syn_ok, margin, nthreads);
 }
 
 /* Vertical group-shuffled decoding: groups gptr[G+1], gvn over VN ids (each
@@ -292,7 +319,7 @@ int ref_decode_vertical(int M, int N, const int32_t* row_ptr, const int32_t* col
                         const int32_t* gvn, const float* llr, int F, int max_iter, int early_stop, double* post,
                         uint8_t* hard, int32_t* iters, uint8_t* syn_ok, int nthreads) {
     return run_job(M, N, row_ptr, col, G, gptr, gvn, 0, 1, llr, F, max_iter, early_stop, post, hard, iters,
-                   syn_ok, nthreads);
+                   syn_ok, NULL, nthreads);
 }
 
 /* The same with one grouping for every iteration. */
@@ -300,5 +327,5 @@ int ref_decode(int M, int N, const int32_t* row_ptr, const int32_t* col, int G, 
                const int32_t* gcn, const float* llr, int F, int max_iter, int early_stop, double* post,
                uint8_t* hard, int32_t* iters, uint8_t* syn_ok, int nthreads) {
     return ref_decode_schedule(M, N, row_ptr, col, G, gptr, gcn, 0, llr, F, max_iter, early_stop, post, hard,
-                               iters, syn_ok, nthreads);
+                               iters, syn_ok, NULL, nthreads);
 }

@@ -7,7 +7,13 @@ moves by one float32 ulp, inf when that changes a decision or the iteration
 count; see oracle.decode_with_sensitivity):
 
 * frames the oracle decodes: identical hard decisions (no exception);
-* wherever the decisions match: identical syndrome flag and iteration count;
+* wherever the decisions match: identical syndrome flag and iteration count,
+  unless the frame's stop iteration is not determined at the posterior
+  tolerance: the oracle's stop margin (``margin``: the smallest change of
+  total LLRs that could move the iteration at which Step 4 stops) is below
+  ATOL. Such a frame may stop at another iteration with the same decisions;
+  its posteriors are then held to the oracle's own posteriors at the GPU's
+  iteration count (``rerun``);
 * well-conditioned frames (decoded, sens < SENS_WELL): every posterior
   within ATOL + RTOL |ref| (1e-3 absolute near zero, 1e-4 relative);
 * other frames with matching decisions: the posterior bound widens by
@@ -64,21 +70,35 @@ def compare(gpu, ref, rtol=RTOL, atol=ATOL, k_sens=K_SENS, pooled=False):
     well = (sens < SENS_WELL) & (ref["syn_ok"] == 1)
     conv = ref["syn_ok"] == 1
     match = np.all(gpu["hard"] == ref["hard"], axis=1)
-    err = np.abs(gpu["post"].astype(np.float64) - ref["post"])
     widen = np.where(well, 0.0, k_sens * np.where(np.isfinite(sens), sens, np.inf))
-    bound = atol + rtol * np.abs(ref["post"]) + widen[:, None]
+    # frames whose stop iteration moves under changes below the posterior
+    # tolerance, and among them those that did stop elsewhere on the GPU:
+    # their posteriors are compared with the oracle's after the GPU's count
+    marginal = ref["margin"] < atol if "margin" in ref else np.zeros(F, dtype=bool)
+    moved = match & (gpu["iters"] != ref["iters"])
+    assert np.all(marginal[moved]), \
+        f"iteration counts differ on {int((moved & ~marginal).sum())} frames whose stop is determined"
+    refpost = ref["post"]
+    if moved.any():
+        idx = np.nonzero(moved)[0]
+        assert "rerun" in ref, "a frame stopped at another iteration and the oracle cannot be rerun"
+        refpost = refpost.copy()
+        refpost[idx] = ref["rerun"](idx, gpu["iters"][idx])
+    err = np.abs(gpu["post"].astype(np.float64) - refpost)
+    bound = atol + rtol * np.abs(refpost) + widen[:, None]
     pok = np.all(err <= bound, axis=1)
-    strict_pok = np.all(err <= atol + rtol * np.abs(ref["post"]), axis=1)
+    strict_pok = np.all(err <= atol + rtol * np.abs(refpost), axis=1)
+    same = match & ~moved
     stats = dict(frames=F, oracle_converged=int(conv.sum()), well_conditioned=int(well.sum()),
                  decision_mismatch=int((~match).sum()),
                  strict_post_miss=int((match & ~strict_pok).sum()),
                  strict_post_miss_well=int((match & well & ~strict_pok).sum()),
                  max_abs_err_well=float(err[well & match].max()) if (well & match).any() else 0.0,
-                 max_abs_err=float(err[match].max()) if match.any() else 0.0)
+                 max_abs_err=float(err[match].max()) if match.any() else 0.0,
+                 stop_marginal=int(marginal.sum()), stop_moved=int(moved.sum()))
     # well-conditioned frames: the bar as stated
     w = well
     assert np.all(match[w]), f"decisions differ on {int((~match & w).sum())} well-conditioned frames"
-    assert np.array_equal(gpu["iters"][w], ref["iters"][w]), "iteration counts differ (well-conditioned)"
     assert np.all(strict_pok[w]), f"posteriors out of bound on {int((w & ~strict_pok).sum())} " \
                                   f"well-conditioned frames (max err {err[w].max()})"
     # decoded frames: same codeword; wherever the decisions match (every
@@ -86,7 +106,7 @@ def compare(gpu, ref, rtol=RTOL, atol=ATOL, k_sens=K_SENS, pooled=False):
     assert np.all(match[conv]), f"decisions differ on {int((~match & conv).sum())} decoded frames"
     if "syn_ok" in gpu:
         assert np.array_equal(gpu["syn_ok"][match], ref["syn_ok"][match]), "syndrome flags differ"
-    assert np.array_equal(gpu["iters"][match], ref["iters"][match]), "iteration counts differ"
+    assert np.array_equal(gpu["iters"][same], ref["iters"][same]), "iteration counts differ"
     # posteriors of every frame with matching decisions, widened where ill-conditioned
     assert np.all(pok[match]), f"posteriors out of the widened bound on {int((match & ~pok).sum())} frames"
     # the frame fraction: >= 99.99% matching, or every mismatch undecoded

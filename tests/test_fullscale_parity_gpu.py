@@ -53,7 +53,8 @@ def test_full_point(sweep, snr):
     print(f"full-scale {REC['ebn0'][snr]} dB: frames {st['frames']}, oracle decoded {st['oracle_converged']}, "
           f"decision mismatches {st['decision_mismatch']} (chaotic {st['undecoded_mismatch_chaotic']}), "
           f"one-ulp control flips {st['control_flips']}, undecoded GPU/oracle {fer_gpu}/{fer_ref}, "
-          f"strict posterior misses {st['strict_post_miss']} (well-conditioned {st['strict_post_miss_well']})")
+          f"strict posterior misses {st['strict_post_miss']} (well-conditioned {st['strict_post_miss_well']}), "
+          f"stop margin below 1e-3 nats {st['stop_marginal']} (stopped at another iteration {st['stop_moved']})")
 
 
 def test_workload_decision_match():

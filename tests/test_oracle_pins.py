@@ -439,3 +439,26 @@ def test_vertical_equals_map_on_trees(seed):
     for groups in ([perm[: n // 2], perm[n // 2:]], [[int(x)] for x in perm]):
         out = oracle.decode_vertical(code, groups, llr[None], max_iter=2 * n, early_stop=False, nthreads=1)
         np.testing.assert_allclose(out["post"][0], want, rtol=0, atol=1e-9)
+
+
+def test_stop_margin_matches_its_definition():
+    """The oracle's stop margin (a diagnostic of the parity bar) equals its
+    definition evaluated on the oracle's posteriors after each iteration:
+    the minimum over the iterations run of (zero syndrome: the smallest |P|
+    of a VN in some check; otherwise: the largest, over failing checks, of
+    the smallest |P| in the check)."""
+    from ldpcgen import workloads as W
+    code = W.code_n96()
+    groups = oracle.windows(code.m, 4, 2, True)
+    llr, _ = make_frames(code.n, 12, 1.5, 0.5, seed=88)
+    r = oracle.decode(code, groups, llr, 10, True)
+    rp, ci = np.asarray(code.row_ptr), np.asarray(code.col_idx)
+    for f in range(12):
+        want = np.inf
+        for l in range(1, int(r["iters"][f]) + 1):
+            P = oracle.decode(code, groups, llr[f:f + 1], l, False)["post"][0]
+            low = np.array([np.abs(P[ci[rp[m]:rp[m + 1]]]).min() for m in range(code.m)])
+            par = np.array([np.bitwise_xor.reduce((P[ci[rp[m]:rp[m + 1]]] < 0).astype(int)) for m in range(code.m)])
+            here = low.min() if not par.any() else low[par == 1].max()
+            want = min(want, here)
+        assert r["margin"][f] == want, f

@@ -138,3 +138,24 @@ def test_sixteen_bit_bar():
     bad = _gpu(ref)
     bad["post"][5, 0] += 100.0
     compare16(bad, ref)
+
+
+def test_stop_moved_only_where_undetermined():
+    """A frame may stop at another iteration (same decisions) only if the
+    oracle's stop margin is below the posterior tolerance; its posteriors
+    are then held to the oracle's result at the GPU's iteration count."""
+    ref = _ref()
+    ref["margin"] = np.full(200, 0.5)
+    g = _gpu(ref)
+    g["iters"][60] += 1
+    with pytest.raises(AssertionError):
+        compare(g, ref)  # stop determined (margin 0.5 nats)
+    ref["margin"][60] = 2e-5
+    with pytest.raises(AssertionError):
+        compare(g, ref)  # undetermined, but no rerun to check the posteriors against
+    ref["rerun"] = lambda idx, it: ref["post"][idx]
+    st = compare(g, ref)
+    assert st["stop_moved"] == 1 and st["stop_marginal"] == 1
+    ref["rerun"] = lambda idx, it: ref["post"][idx] + 1.0
+    with pytest.raises(AssertionError):
+        compare(g, ref)  # posteriors at the moved stop out of bound
