@@ -29,7 +29,7 @@ struct HbmArgs {
     int32_t sgn_lds;         // nonzero: per-VN sign words in dynamic LDS (hbm_sign_bytes)
     int32_t dslot_lds;       // nonzero (with sgn_lds): delta slots in LDS after them (hbm_slot_bytes)
     int32_t max_slots;       // delta slots of the largest group
-    float ymax, cmin;
+    float ymax;
 };
 
 // Static LDS of the HBM-tier kernel (slot bookkeeping), bytes, an upper bound.

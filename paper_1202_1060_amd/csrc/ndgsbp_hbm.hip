@@ -192,7 +192,7 @@ __global__ __launch_bounds__(HbmMaxThreads<D>::value) void ndgsbp_hbm_kernel(Hbm
                     lo[k] = zero_old ? 0.0f : old;
                     real[k] = pa[k] != p.pad_b;
                 }
-                cn_core<M, D, UNI, 1>(pv, lo, real, a.ymax, a.cmin, st, wvals);
+                cn_core<M, D, UNI, 1>(pv, lo, real, a.ymax, st, wvals);
 #pragma unroll
                 for (int k = 0; k < D; ++k) {
                     // a posterior target takes w; a delta slot takes this

@@ -445,7 +445,6 @@ void set_launch_constants(DecodeArgs& a, uint32_t flags, size_t lds) {
     a.packed = (flags & LDPC_FLAG_OUT_PACKED) ? 1 : 0;
     a.sh_offset = (int32_t)(lds - 16);
     a.ymax = (float)(kXMax * kLog2e);
-    a.cmin = (float)kXMin;
 }
 
 // Launch class of a batched problem: kernel variant, and with size
@@ -764,7 +763,6 @@ int decode_hbm(ldpc_code* c, const float* llr, int32_t num_frames, int32_t max_i
     a.early_stop = (flags & LDPC_FLAG_EARLY_STOP) ? 1 : 0;
     a.packed = (flags & LDPC_FLAG_OUT_PACKED) ? 1 : 0;
     a.ymax = (float)(kXMax * kLog2e);
-    a.cmin = (float)kXMin;
     if (scratch) {
         const int64_t fit = (int64_t)(scratch->hbm_bytes / tile_bytes);
         if (fit < 1)

@@ -17,13 +17,13 @@ namespace ndgsbp {
 constexpr double kLog2e = 1.4426950408889634;
 constexpr double kLn2 = 0.6931471805599453;
 // Magnitude clamp of the CN update, in nats: [phi(30), 30] at both phi inputs
-// of the sign-magnitude rule. phi(30) = 2 atanh(e^-30) = 2 e^-30 to double
-// precision. In complement form the clamp of the phi sum S to [phi(30), 30]
-// is a clamp of c = 1 - e^-S to [1 - e^-phi(30), 1 - e^-30]: the lower bound
-// is phi(30) to double precision, the upper bound rounds to 1 in FP32. The
-// lower clamp of |x| needs no instruction in FP32 (cn_core).
+// of the sign-magnitude rule (phi(30) = 2 atanh(e^-30), about 1.87e-13). In
+// pair form the clamp of the phi sum to [phi(30), 30] is a clamp of the
+// output magnitude phi(sum) to [phi(30), 30]; the decoder clamps it to
+// [0, 30] (the two lower bounds differ by 1.9e-13 nats, which no FP32 sum
+// with a posterior keeps), and the lower clamp of |x| needs no instruction
+// in FP32 (cn_core).
 constexpr double kXMax = 30.0;
-constexpr double kXMin = 1.8715245937680347e-13;
 
 // Table layout (built by ldpc_code_create). H lanes share a CN (1, 2 or 4);
 // D is the padded CN degree of the kernel variant (a multiple of H, at least
@@ -94,7 +94,6 @@ struct DecodeArgs {
     int32_t packed;       // hard decisions packed 8 per byte (LSB first)
     int32_t sh_offset;    // byte offset of the workgroup state (frame, flags, problem)
     float ymax;           // upper clamp of |VN->CN message|, log2 units
-    float cmin;           // lower clamp of the complement 1 - prod tanh
 };
 
 struct LaunchShape {

@@ -157,7 +157,7 @@ __device__ __forceinline__ void cn_visit(const DecodeArgs& a, const Problem& p, 
         pv[k] = lds_f32(r.pa[k]);
         real[k] = r.pa[k] != p.pad_b;
     }
-    cn_core<M, DH, UNI, H>(pv, lo, real, a.ymax, a.cmin, st, wv);
+    cn_core<M, DH, UNI, H>(pv, lo, real, a.ymax, st, wv);
     if constexpr (VERT) {
 #pragma unroll
         for (int k = 0; k < DH; ++k)
