@@ -278,19 +278,56 @@ __device__ __forceinline__ Problem get_problem(const DecodeArgs& a, int idx) {
     return __builtin_bit_cast(Problem, pw);
 }
 
-template <class M, int D, int H>
-__device__ __forceinline__ void init_frame(const Problem& p, int frame, int tid, int nt) {
-    const float* y = p.llr + (size_t)frame * p.n;
-    for (int v = tid; v < p.n; v += nt) lds_f32(4u * v) = y[v] * kLog2eF + 0.0f;  // + 0 turns -0.0 into +0.0
-    // posterior n: scratch of padding edges; n + 1: 0, padding of syndrome rows
-    if (tid < 2) lds_f32(4u * (p.n + tid)) = 0.0f;
-    // messages start at 0 (every format stores +0 as all-zero bits)
-    const int words = p.m * H * Row<M, D / H>::kWords;
-    for (int q = tid; q < words; q += nt) lds_i32((uint32_t)p.l_offset + 4u * q) = 0;
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x4v __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(3))) f32x4 lds_f32x4;
+typedef __attribute__((address_space(3))) u32x4v lds_u32x4;
+
+// A frame's 16-byte words are read and written whole when n is a multiple
+// of 4 and the buffer is 16-byte aligned (every frame then is).
+__device__ __forceinline__ bool quad_frames(const void* buf, int n) {
+    return (n & 3) == 0 && (reinterpret_cast<uintptr_t>(buf) & 15) == 0;
 }
 
+// The lane index, opaque to the compiler when OPAQUE, so that the addresses
+// of the 16-byte frame-start and output loops are formed where they are
+// used instead of being hoisted out of the frame loop, where they would hold
+// registers through every CN phase.
+template <bool OPAQUE>
+__device__ __forceinline__ int fresh_lane(int tid) {
+    if constexpr (OPAQUE) asm volatile("" : "+v"(tid));
+    return tid;
+}
+
+template <class M, int D, int H, bool VEC>
+__device__ __forceinline__ void init_frame(const Problem& p, int frame, int tid_, int nt) {
+    const int tid = fresh_lane<VEC>(tid_);
+    const float* y = p.llr + (size_t)frame * p.n;
+    // posteriors in log2 units; + 0 turns -0.0 into +0.0
+    if (VEC && quad_frames(p.llr, p.n)) {
+        const f32x4* y4 = reinterpret_cast<const f32x4*>(y);
+        for (int q = tid; q < (p.n >> 2); q += nt) *(lds_f32x4*)(size_t)(16u * q) = y4[q] * kLog2eF + 0.0f;
+    } else {
+        for (int v = tid; v < p.n; v += nt) lds_f32(4u * v) = y[v] * kLog2eF + 0.0f;
+    }
+    // posterior n: scratch of padding edges; n + 1: 0, padding of syndrome rows
+    if (tid < 2) lds_f32(4u * (p.n + tid)) = 0.0f;
+    // messages start at 0 (every format stores +0 as all-zero bits); the
+    // message area starts on 16 bytes and is padded to 16
+    if (VEC) {
+        const int quads = (p.m * H * Row<M, D / H>::kWords + 3) >> 2;
+        for (int q = tid; q < quads; q += nt)
+            *(lds_u32x4*)(size_t)((uint32_t)p.l_offset + 16u * q) = u32x4v{0u, 0u, 0u, 0u};
+    } else {
+        const int words = p.m * H * Row<M, D / H>::kWords;
+        for (int q = tid; q < words; q += nt) lds_i32((uint32_t)p.l_offset + 4u * q) = 0;
+    }
+}
+
+template <bool VEC>
 __device__ __forceinline__ void write_outputs(const DecodeArgs& a, const Problem& p, int frame, int used, int fail,
-                                              int tid, int nt) {
+                                              int tid_, int nt) {
+    const int tid = fresh_lane<VEC>(tid_);
     float* po = p.post ? p.post + (size_t)frame * p.n : nullptr;
     if (a.packed) {
         // byte q holds d_{8q} .. d_{8q+7}, bit k = d_{8q+k}; bits past n are 0
@@ -309,10 +346,21 @@ __device__ __forceinline__ void write_outputs(const DecodeArgs& a, const Problem
             for (int v = tid; v < p.n; v += nt) po[v] = lds_f32(4u * v) * kLn2F;
     } else {
         uint8_t* hd = p.hard + (size_t)frame * p.n;
-        for (int v = tid; v < p.n; v += nt) {
-            const float x = lds_f32(4u * v);
-            hd[v] = x < 0.0f ? 1 : 0;
-            if (po) po[v] = x * kLn2F;
+        if (VEC && (p.n & 3) == 0 && (reinterpret_cast<uintptr_t>(p.hard) & 3) == 0 && (!po || quad_frames(p.post, p.n))) {
+            // four VNs per lane: one 16-byte LDS read, a 4-byte and a 16-byte store
+            for (int q = tid; q < (p.n >> 2); q += nt) {
+                const f32x4 x = *(const lds_f32x4*)(size_t)(16u * q);
+                const uint32_t bits = (x.x < 0.0f ? 1u : 0u) | (x.y < 0.0f ? 1u << 8 : 0u) |
+                                      (x.z < 0.0f ? 1u << 16 : 0u) | (x.w < 0.0f ? 1u << 24 : 0u);
+                reinterpret_cast<uint32_t*>(hd)[q] = bits;
+                if (po) reinterpret_cast<f32x4*>(po)[q] = x * kLn2F;
+            }
+        } else {
+            for (int v = tid; v < p.n; v += nt) {
+                const float x = lds_f32(4u * v);
+                hd[v] = x < 0.0f ? 1 : 0;
+                if (po) po[v] = x * kLn2F;
+            }
         }
     }
     if (tid == 0) {
@@ -356,11 +404,15 @@ __global__ __launch_bounds__(MaxThreads<D>::value) void ndgsbp_kernel(DecodeArgs
     int pid = TABLE ? __builtin_amdgcn_readfirstlane(lds_i32(sh + 12)) : 0;
     Problem p = get_problem<TABLE>(a, pid);
     int used = 0;
-    if (frame >= 0) init_frame<M, D, H>(p, frame, tid, nt);
-    // the first visit of every lane is fetched one group ahead
+    if (frame >= 0) init_frame<M, D, H, !TABLE>(p, frame, tid, nt);
+    // the first visit of every lane is fetched one group ahead, and so are
+    // the group's visit and fix-up ranges (carried in scalar registers, so
+    // that a group waits on one round of table loads, not three)
     VisitRegs<DH> nxt;
-    bool have_nxt = vitem < table_i32(p.visit_ptr, 1);
-    if (have_nxt) load_visit<DH, H>(p, 0, vitem, lh, nxt);
+    int jn0 = table_i32(p.visit_ptr, 0), jn1 = table_i32(p.visit_ptr, 1);
+    int qn0 = table_i32(p.fix_ptr, 0), qn1 = table_i32(p.fix_ptr, 1);
+    bool have_nxt = vitem < jn1 - jn0;
+    if (have_nxt) load_visit<DH, H>(p, jn0, vitem, lh, nxt);
     // rows of this lane's first SYNK checks, kept for the whole decode
     SynRows<SD, D, SYNK> srow;
     srow.load(p, tid, nt);
@@ -375,15 +427,17 @@ __global__ __launch_bounds__(MaxThreads<D>::value) void ndgsbp_kernel(DecodeArgs
             const int g = gb + gi;
             const VisitRegs<DH> cur = nxt;
             const bool have_cur = have_nxt;
+            const int j0 = jn0, j1 = jn1, q0 = qn0, q1 = qn1;
             const int gn = gi + 1 == p.G ? gb_next : g + 1;
-            const int jn0 = table_i32(p.visit_ptr, gn), jn1 = table_i32(p.visit_ptr, gn + 1);
+            jn0 = table_i32(p.visit_ptr, gn);
+            jn1 = table_i32(p.visit_ptr, gn + 1);
+            qn0 = table_i32(p.fix_ptr, gn);
+            qn1 = table_i32(p.fix_ptr, gn + 1);
             have_nxt = vitem < jn1 - jn0;
             if (have_nxt) load_visit<DH, H>(p, jn0, vitem, lh, nxt);
             // this lane's first fix-up entry of the group, fetched before the CN phase
-            const int q0 = table_i32(p.fix_ptr, g), q1 = table_i32(p.fix_ptr, g + 1);
             const uint2 fix0 = q0 + tid < q1 ? p.fix[q0 + tid] : make_uint2(0u, 0u);
             if (have_cur) cn_visit<M, D, UNI, H, VERT>(a, p, cur, lh);
-            const int j0 = table_i32(p.visit_ptr, g), j1 = table_i32(p.visit_ptr, g + 1);
             for (int item = vitem + nvitem; item < j1 - j0; item += nvitem) {
                 VisitRegs<DH> extra;
                 load_visit<DH, H>(p, j0, item, lh, extra);
@@ -441,7 +495,7 @@ __global__ __launch_bounds__(MaxThreads<D>::value) void ndgsbp_kernel(DecodeArgs
         const int fail = lds_i32(fl);
         if (!((a.early_stop && !fail) || used == p.max_iter)) continue;
         // finished: outputs, then the next frame (of this or another problem)
-        write_outputs(a, p, frame, used, fail, tid, nt);
+        write_outputs<!TABLE>(a, p, frame, used, fail, tid, nt);
         if (tid == 0) claim_frame(a, sh);
         __syncthreads();
         frame = __builtin_amdgcn_readfirstlane(lds_i32(sh));
@@ -460,11 +514,15 @@ __global__ __launch_bounds__(MaxThreads<D>::value) void ndgsbp_kernel(DecodeArgs
                 }
             }
             if (reload) {
-                have_nxt = vitem < table_i32(p.visit_ptr, 1);
-                if (have_nxt) load_visit<DH, H>(p, 0, vitem, lh, nxt);
+                jn0 = table_i32(p.visit_ptr, 0);
+                jn1 = table_i32(p.visit_ptr, 1);
+                qn0 = table_i32(p.fix_ptr, 0);
+                qn1 = table_i32(p.fix_ptr, 1);
+                have_nxt = vitem < jn1 - jn0;
+                if (have_nxt) load_visit<DH, H>(p, jn0, vitem, lh, nxt);
             }
             gb = 0;
-            init_frame<M, D, H>(p, frame, tid, nt);
+            init_frame<M, D, H, !TABLE>(p, frame, tid, nt);
         }
         __syncthreads();
     }
