@@ -12,8 +12,8 @@
 //     CN phase: H lanes per CN visit (H = 1, 2 or 4). For each edge (m, n) a
 //       lane forms the VN->CN message as posterior minus old message (equal to
 //       eq. (2) because the posterior is the total of eq. (3)), evaluates
-//       eq. (1) in complement-product form (ndgsbp_math.h) with exclusive
-//       prefix/suffix combinations, stores the new message and adds it back
+//       eq. (1) in pair form (ndgsbp_math.h) with exclusive prefix/suffix
+//       combinations, stores the new message and adds it back
 //       into the posterior: directly when the VN has no other edge in the
 //       group, else as a delta;
 //     barrier;
