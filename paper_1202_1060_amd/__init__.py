@@ -198,6 +198,10 @@ def hard_width(n: int, packed: bool) -> int:
 
 
 def _check_outputs(out, F, n, packed):
+    for k in ("hard", "post", "iters", "syn_ok"):
+        t = out.get(k)
+        if t is not None and (not t.is_cuda or not t.is_contiguous()):
+            raise ValueError("%s must be a contiguous device tensor" % k)
     if tuple(out["hard"].shape) != (F, hard_width(n, packed)) or out["hard"].dtype != torch.uint8:
         raise ValueError("hard must be a (F, %d) uint8 tensor" % hard_width(n, packed))
     if tuple(out["iters"].shape) != (F,) or out["iters"].dtype != torch.int32:

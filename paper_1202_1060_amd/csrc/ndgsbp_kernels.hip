@@ -44,6 +44,11 @@ typedef __attribute__((address_space(3))) int lds_int;
 typedef __attribute__((address_space(3))) uint32_t lds_u32;
 __device__ __forceinline__ lds_float& lds_f32(uint32_t byte_off) { return *(lds_float*)(size_t)byte_off; }
 __device__ __forceinline__ lds_int& lds_i32(uint32_t byte_off) { return *(lds_int*)(size_t)byte_off; }
+// A flag that other lanes set during the same phase, read afresh every time
+// (a plain read may be kept in a register across a loop).
+__device__ __forceinline__ int lds_flag(uint32_t byte_off) {
+    return *(volatile __attribute__((address_space(3))) int*)(size_t)byte_off;
+}
 
 // Reads of the code tables, which no kernel writes: through the constant
 // address space, so wavefront-uniform indices become scalar loads.
@@ -475,7 +480,6 @@ __global__ __launch_bounds__(MaxThreads<D>::value) void ndgsbp_kernel(DecodeArgs
             if (x >> 31) lds_i32(fl) = 1;
         }
         for (int c = tid + SYNK * nt; c < p.m; c += nt) {
-            if (lds_i32(fl)) break;
             const uint4* col = reinterpret_cast<const uint4*>(p.syn_col + (size_t)c * SD);
             uint32_t e[SD];
 #pragma unroll
@@ -486,6 +490,9 @@ __global__ __launch_bounds__(MaxThreads<D>::value) void ndgsbp_kernel(DecodeArgs
                 e[4 * q + 2] = w.z;
                 e[4 * q + 3] = w.w;
             }
+            // stop once any check of the frame has failed (the row load above
+            // is then unused)
+            if (lds_flag(fl)) break;
             uint32_t x = 0;
 #pragma unroll
             for (int k = 0; k < D; ++k) x ^= __float_as_uint(lds_f32(e[k]));

@@ -106,6 +106,39 @@ def test_deterministic_bitwise():
         assert np.array_equal(a[k], b[k]), k
 
 
+def test_unaligned_buffers_equal_aligned():
+    """Buffers that are not 16-byte aligned (LLRs and posteriors 4 bytes
+    past it, hard decisions 1 byte past) take the one-word frame start and
+    output loops of the one-code kernel; the results equal those of aligned
+    buffers (the 16-byte loops) bit for bit."""
+    rec = W.SWEEP
+    code = W.CODES[rec["code"]]()
+    llr, _ = W.frames(rec, 2, num_frames=300)
+    F, n = llr.shape
+    dcode = nd.Code(code, windows=rec["windows"])
+    try:
+        a = gpu_decode(dcode, llr, rec["max_iter"], True)
+        dev = torch.device("cuda:0")
+        lb = torch.zeros(F * n + 4, dtype=torch.float32, device=dev)
+        x = lb[1:1 + F * n].view(F, n)
+        x.copy_(torch.from_numpy(llr))
+        hb = torch.zeros(F * n + 4, dtype=torch.uint8, device=dev)
+        pb = torch.zeros(F * n + 4, dtype=torch.float32, device=dev)
+        out = dict(hard=hb[1:1 + F * n].view(F, n), post=pb[1:1 + F * n].view(F, n),
+                   iters=torch.empty(F, dtype=torch.int32, device=dev),
+                   syn_ok=torch.empty(F, dtype=torch.uint8, device=dev))
+        assert x.data_ptr() % 16 == 4 and out["hard"].data_ptr() % 4 == 1
+        nd.decode(dcode, x, rec["max_iter"], early_stop=True, out=out)
+        torch.cuda.synchronize()
+        for k in a:
+            assert np.array_equal(out[k].cpu().numpy(), a[k]), k
+        # the bytes around the outputs are untouched
+        assert int(hb[0]) == 0 and int(hb[-3:].sum()) == 0
+        assert float(pb[0]) == 0.0 and float(pb[-3:].abs().sum()) == 0.0
+    finally:
+        dcode.close()
+
+
 def test_explicit_groups_equal_windows():
     rec = W.SWEEP
     code = W.CODES[rec["code"]]()
