@@ -450,9 +450,16 @@ __global__ __launch_bounds__(MaxThreads<D>::value) void ndgsbp_kernel(DecodeArgs
             }
             __syncthreads();
             if (q1 > q0) {
-                if (q0 + tid < q1) fold_deltas(p, fix0);
+                // the waves that fold are the group's critical path (everyone
+                // else waits at the barrier): they issue ahead of the other
+                // workgroups' CN phases on the same SIMD
+                if (q0 + tid < q1) {
+                    __builtin_amdgcn_s_setprio(2);
+                    fold_deltas(p, fix0);
+                }
                 for (int q = q0 + tid + nt; q < q1; q += nt) fold_deltas(p, p.fix[q]);
                 __syncthreads();
+                __builtin_amdgcn_s_setprio(0);
             }
         }
         gb = gb_next;
@@ -465,6 +472,9 @@ __global__ __launch_bounds__(MaxThreads<D>::value) void ndgsbp_kernel(DecodeArgs
         if (tid == 0) lds_i32(fo) = 0;
         const bool check = a.early_stop || used == p.max_iter;
         if (!check) continue;
+        // the syndrome and a frame change are short phases between barriers:
+        // ahead of other workgroups' CN phases too, behind the fold
+        __builtin_amdgcn_s_setprio(1);
         // the sign bit of a posterior is its hard decision (no -0.0); a lane
         // stops once any check has been seen to fail
         {
@@ -500,7 +510,10 @@ __global__ __launch_bounds__(MaxThreads<D>::value) void ndgsbp_kernel(DecodeArgs
         }
         __syncthreads();
         const int fail = lds_i32(fl);
-        if (!((a.early_stop && !fail) || used == p.max_iter)) continue;
+        if (!((a.early_stop && !fail) || used == p.max_iter)) {
+            __builtin_amdgcn_s_setprio(0);
+            continue;
+        }
         // finished: outputs, then the next frame (of this or another problem)
         write_outputs<!TABLE>(a, p, frame, used, fail, tid, nt);
         if (tid == 0) claim_frame(a, sh);
@@ -532,6 +545,7 @@ __global__ __launch_bounds__(MaxThreads<D>::value) void ndgsbp_kernel(DecodeArgs
             init_frame<M, D, H, !TABLE>(p, frame, tid, nt);
         }
         __syncthreads();
+        __builtin_amdgcn_s_setprio(0);
     }
 
     // the last workgroup out resets the launch's counters for the next launch
