@@ -296,7 +296,6 @@ def bench_hbm(args, torch, nd, W, dev, log, sweep_llr, sweep_k):
     2.0 dB). Algorithmic HBM bytes per edge update: posterior read + write
     (8 B) + message read + write (2 x message size)."""
     from paper_1202_1060_amd import _native
-    from ldpcgen import make_frames
     from ldpcgen.codes import qc_code, base_mask
     stream = torch.cuda.current_stream(dev)
 
@@ -341,8 +340,12 @@ def bench_hbm(args, torch, nd, W, dev, log, sweep_llr, sweep_k):
     del x
     big = qc_code(base_mask("1/2", 1030), 704, 1030)
     bcode = nd.Code(big, windows=(12, 176, 1))
-    llr, _ = make_frames(big.n, args.hbm_big_frames, 2.0, 0.5, seed=1031)
-    x = torch.from_numpy(llr).to(dev)
+    # all-zero codeword over BPSK/AWGN at 2.0 dB (rate 1/2), drawn on the
+    # device: 131072 frames are 8.9 GB of LLRs
+    sigma = float(np.sqrt(1.0 / (2 * 0.5 * 10 ** (2.0 / 10))))
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(1031)
+    x = (2.0 / sigma ** 2) * (1.0 + sigma * torch.randn(args.hbm_big_frames, big.n, device=dev, generator=gen))
     for msg in ("fp32", "fp16"):
         r, _ = run(bcode, x, 20, msg, args.hbm_steps, False)
         r["gbit_s"] = x.shape[0] * (big.n - big.m) / (r["ms"] * 1e-3) / 1e9
@@ -350,7 +353,8 @@ def bench_hbm(args, torch, nd, W, dev, log, sweep_llr, sweep_k):
         log(f"hbm tier, n=16896 {msg}: {r['gbit_s']:.2f} Gbit/s, {r['algorithmic_gb_s']:.0f} GB/s")
     out["n16896"] = {"frames": int(x.shape[0]), "lds_bytes_fp32": bcode.info["lds_bytes_fp32"],
                      "lds_limit": bcode.info["lds_limit"], "info_bits_per_frame": big.n - big.m,
-                     "note": "all-zero codeword, 2.0 dB, 12 windows overlap 176, I_max 20, syndrome stop; info bits at the design rate (n - m)"}
+                     "note": "all-zero codeword, 2.0 dB (LLRs drawn on the device), 12 windows overlap 176, "
+                             "I_max 20, syndrome stop; info bits at the design rate (n - m)"}
     bcode.close()
     return out
 
@@ -567,7 +571,9 @@ def main():
     ap.add_argument("--no-serving", action="store_true", help="skip the serving leg")
     ap.add_argument("--no-hbm", action="store_true", help="skip the HBM-tier leg")
     ap.add_argument("--hbm-steps", type=int, default=3)
-    ap.add_argument("--hbm-big-frames", type=int, default=32768)
+    ap.add_argument("--hbm-big-frames", type=int, default=131072,
+                    help="frames of the n=16896 HBM-tier leg (512 per 64-slot tile and CU: the tile's "
+                         "tail, when its last frames run with idle slots, is amortised over 8 refills)")
     ap.add_argument("--serve-requests", type=int, default=30000)
     ap.add_argument("--serve-plain-requests", type=int, default=3000)
     ap.add_argument("--serve-verify", type=int, default=2000)
