@@ -156,12 +156,16 @@ __device__ __forceinline__ void cn_visit(const DecodeArgs& a, const Problem& p, 
     float pv[DH], lo[DH], wv[DH];
     bool real[DH];
     typename M::T st[DH];
+    // the visit's LDS loads issue ahead of other waves' arithmetic, so that
+    // more of them are in flight; the arithmetic runs at the base priority
+    __builtin_amdgcn_s_setprio(1);
     R::load(row, lo);
 #pragma unroll
     for (int k = 0; k < DH; ++k) {
         pv[k] = lds_f32(r.pa[k]);
         real[k] = r.pa[k] != p.pad_b;
     }
+    __builtin_amdgcn_s_setprio(0);
     cn_core<M, DH, UNI, H>(pv, lo, real, a.ymax, st, wv);
     if constexpr (VERT) {
 #pragma unroll
