@@ -146,7 +146,7 @@ __device__ __forceinline__ void load_visit(const Problem& p, int j0, int item, i
 // the add-back into LDS. VERT (the vertical, VN-group schedule): an edge
 // whose add-back target is the scratch word (ta = 4n) is an input only, its
 // VN being outside the group: its message keeps its old bits.
-template <class M, int D, bool UNI, int H, bool VERT>
+template <class M, int D, bool UNI, int H, bool VERT, bool LATE = false>
 __device__ __forceinline__ void cn_visit(const DecodeArgs& a, const Problem& p, const VisitRegs<D / H>& r,
                                          uint32_t h) {
     constexpr int DH = D / H;
@@ -157,15 +157,17 @@ __device__ __forceinline__ void cn_visit(const DecodeArgs& a, const Problem& p, 
     bool real[DH];
     typename M::T st[DH];
     // the visit's LDS loads issue ahead of other waves' arithmetic, so that
-    // more of them are in flight; the arithmetic runs at the base priority
-    __builtin_amdgcn_s_setprio(1);
+    // more of them are in flight; the arithmetic runs at the base priority,
+    // which is raised (LATE) for the visits of a group's later passes: the
+    // waves that run them are the ones the group barrier waits for
+    __builtin_amdgcn_s_setprio(LATE ? 2 : 1);
     R::load(row, lo);
 #pragma unroll
     for (int k = 0; k < DH; ++k) {
         pv[k] = lds_f32(r.pa[k]);
         real[k] = r.pa[k] != p.pad_b;
     }
-    __builtin_amdgcn_s_setprio(0);
+    __builtin_amdgcn_s_setprio(LATE ? 1 : 0);
     cn_core<M, DH, UNI, H>(pv, lo, real, a.ymax, st, wv);
     if constexpr (VERT) {
 #pragma unroll
@@ -450,8 +452,9 @@ __global__ __launch_bounds__(MaxThreads<D>::value) void ndgsbp_kernel(DecodeArgs
             for (int item = vitem + nvitem; item < j1 - j0; item += nvitem) {
                 VisitRegs<DH> extra;
                 load_visit<DH, H>(p, j0, item, lh, extra);
-                cn_visit<M, D, UNI, H, VERT>(a, p, extra, lh);
+                cn_visit<M, D, UNI, H, VERT, true>(a, p, extra, lh);
             }
+            __builtin_amdgcn_s_setprio(0);
             __syncthreads();
             if (q1 > q0) {
                 // the waves that fold are the group's critical path (everyone
